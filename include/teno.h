@@ -1,0 +1,179 @@
+/*
+ * teno.h -- C-ABI of libteno.so: the TENO5-LAD semi-discrete Euler
+ * right-hand side and its SSP-RK3 drivers on one MI355X (gfx950) GPU.
+ *
+ * Method: Peng, Li, Shen, Liu, Zhang, "An efficient targeted ENO scheme with
+ * local adaptive dissipation for compressible flow simulation",
+ * arXiv:2003.09145.
+ *   - semi-discrete conservative form du/dt = -(f_{i+1/2} - f_{i-1/2})/dx,
+ *     one direction at a time, summed over x, y, z           (Sec. 2, eq 2.2)
+ *   - global Lax-Friedrichs flux splitting, reconstruction in characteristic
+ *     space                                                    (Sec. 4)
+ *   - fifth-order TENO reconstruction: candidate fluxes, Jiang-Shu
+ *     smoothness indicators, tau_5, scale separation, cutoff  (Sec. 2,
+ *     eq 2.4-2.15)
+ *   - locally adaptive cutoff C_T = Lad(m), m = B_l + floor(theta (B_u-B_l)),
+ *     theta = 1 / (1 + max_k chi~_k / H)                      (Sec. 3,
+ *     eq 3.1-3.4)
+ *   - SSP-RK3 time stepping and CFL time step                 (Sec. 4,
+ *     eq 4.1-4.3, eq dt1, eq dt2)
+ *   - Euler equations of an ideal gas                          (Sec. 4.2, eq 4.7)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Fields: FP64, structure of arrays, component-major, x fastest:
+ *     U[c * ncell + (k * ny + j) * nx + i],  ncell = nx * ny * nz,
+ * components c = rho, rho*u_x, [rho*u_y], [rho*u_z], E (ncomp = ndim + 2),
+ * interior cells only (ghost cells are synthesised on chip).
+ *
+ * Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ * tensors); every other pointer is a host pointer.  The caller owns every
+ * buffer.  Entry points that take a stream enqueue work on it and return
+ * without synchronising; device-detected errors are reported through the
+ * device control block (teno_ctrl.status).  Host-side validation failures
+ * return TENO_ERR_ARG and enqueue nothing.  No exceptions cross the ABI.
+ * `stream` is a hipStream_t (NULL = the default stream).
+ */
+#ifndef TENO_H_
+#define TENO_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define TENO_OK 0
+#define TENO_ERR_ARG 1          /* invalid argument; nothing was enqueued       */
+#define TENO_ERR_DEVICE 2       /* a HIP call failed                            */
+#define TENO_ERR_NONPHYSICAL 3  /* rho <= 0, p <= 0 or a non-finite value seen  */
+
+/* Boundary types, applied at both ends of an axis (Sec. 4.1: periodic;
+ * Sec. 4.2: zero-gradient; Sec. 4.2 eq 4.11: reflecting).  Three ghost cells
+ * per side: periodic wrap; copy of the edge cell; mirror image with the
+ * normal momentum negated. */
+#define TENO_BC_PERIODIC 0
+#define TENO_BC_TRANSMISSIVE 1
+#define TENO_BC_REFLECTIVE 2
+
+/* Cutoff schemes: the locally adaptive C_T (Sec. 3), a fixed C_T (TENO5,
+ * Sec. 2 eq 2.14), or every stencil kept (the linear upwind scheme eq 2.3). */
+#define TENO_SCHEME_LAD 0
+#define TENO_SCHEME_FIXED_CT 1
+#define TENO_SCHEME_LINEAR5 2
+
+/* Grid, gas and scheme parameters (host struct, read at call time). */
+typedef struct teno_grid {
+    int32_t ndim;      /* 1, 2 or 3                                             */
+    int32_t n[3];      /* cells per axis; axes >= ndim must be 1; n >= 3 on the
+                          swept axes                                            */
+    double dx[3];      /* uniform spacing per axis (> 0)                        */
+    int32_t bc[3];     /* TENO_BC_* per axis                                    */
+    int32_t scheme;    /* TENO_SCHEME_*                                         */
+    double gamma;      /* ratio of specific heats (> 1), eq 4.7                 */
+    double ct_fixed;   /* C_T of TENO_SCHEME_FIXED_CT                           */
+    double H;          /* LAD intensity threshold, eq 3.2 (paper: 10)           */
+    int32_t Bl, Bu;    /* LAD magnitude bounds, eq 3.1 (paper: 4, 10);
+                          0 <= Bl <= Bu <= 20                                   */
+    double eps;        /* epsilon of eq 2.8 and eq 3.2 (paper: 1e-6)            */
+    int32_t flags;     /* TENO_FLAG_* (0 for normal use)                        */
+    int32_t reserved_;
+} teno_grid;
+
+/* teno_grid.flags: evaluate every cutoff decision with the literal formula
+ * instead of the certified fast path (identical results, slower; for
+ * verification and timing comparisons). */
+#define TENO_FLAG_LITERAL_DECISIONS 1
+
+/* Time-stepping control block.  Lives in DEVICE memory so that step loops
+ * never synchronise with the host and can be captured in a HIP graph. */
+typedef struct teno_ctrl {
+    double t;            /* current time                                         */
+    double t_end;        /* the step is clipped so that t never passes t_end     */
+    double cfl;          /* CFL number sigma of eq dt1 / eq dt2                   */
+    double dt;           /* dt of the last step (input in replay mode)           */
+    double alpha[3][3];  /* LF speeds [stage][axis] used by the last step
+                            (input in replay mode)                               */
+    int32_t status;      /* sticky TENO_OK / TENO_ERR_NONPHYSICAL                */
+    int32_t replay;      /* 0: dt and alpha from the state; 1: taken from here   */
+    int64_t nsteps;      /* number of completed steps                            */
+    int32_t active;      /* internal: 1 while the current step is running        */
+    int32_t pad_;
+} teno_ctrl;
+
+/* Bytes of device workspace that teno_rhs / teno_step / teno_rhs_adjoint need
+ * for this grid (three state-sized buffers plus a small scratch area).
+ * Returns 0 for an invalid grid. */
+size_t teno_workspace_bytes(const teno_grid* g);
+
+/* Fill a device control block: t = t0, t_end, cfl, replay = 0, status = OK,
+ * nsteps = 0 (enqueued on `stream`). */
+int teno_ctrl_init(teno_ctrl* ctrl_dev, double t0, double t_end, double cfl,
+                   void* stream);
+
+/* dUdt_dev = L(U_dev): the semi-discrete RHS of eq 2.2 summed over the axes
+ * in the order x, y, z (dUdt = 0 - dF_x/dx - dF_y/dy - dF_z/dz), with
+ * characteristic TENO5-LAD reconstruction of global Lax-Friedrichs split
+ * fluxes (Sec. 2-4).
+ *   alpha_in_dev   nullable: 3 doubles of frozen LF speeds per axis; when
+ *                  null they are computed from U as max_i (|u_d| + c).
+ *   alpha_out_dev  nullable: receives the speeds used (3 doubles).
+ *   status_dev     nullable: int32, set to TENO_ERR_NONPHYSICAL if U has a
+ *                  cell with rho <= 0, p <= 0 or a non-finite sound speed
+ *                  (only checked when alpha is computed).
+ *   ws_dev, ws_bytes  workspace of at least teno_workspace_bytes(g).
+ * U_dev and dUdt_dev must not overlap. */
+int teno_rhs(const teno_grid* g, const double* U_dev, double* dUdt_dev,
+             const double* alpha_in_dev, double* alpha_out_dev,
+             int32_t* status_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* As teno_rhs, and also writes the cutoff decisions of every scalar
+ * reconstruction: per axis d (x, y, z), per line, per face phi = i + 1 in
+ * [0, n_d], 2*ncomp bytes (characteristic field s, sign + then -), each byte
+ * m | (mask << 5) with m the ladder exponent (0 unless LAD) and mask bit k =
+ * delta_k of eq 2.14.  Lines of axis x are numbered k*ny + j, of axis y
+ * k*nx + i, of axis z j*nx + i.  decisions_dev holds
+ * sum_d (ncell / n_d) (n_d + 1) 2 ncomp bytes. */
+int teno_rhs_debug(const teno_grid* g, const double* U_dev, double* dUdt_dev,
+                   const double* alpha_in_dev, double* alpha_out_dev,
+                   int32_t* status_dev, uint8_t* decisions_dev, void* ws_dev,
+                   size_t ws_bytes, void* stream);
+
+/* One direction of eq 2.2 (one sweep kernel launch):
+ *   Rout = Rin - (F^_{i+1/2} - F^_{i-1/2}) / dx_axis      (Rin == NULL: 0),
+ * with F^ the characteristic TENO5-LAD flux of global LF split fluxes using
+ * alpha_dev[axis] (alpha_dev: 3 device doubles).  Rin may equal Rout (each
+ * cell is read and written by one thread); U must not overlap Rout.  This is
+ * the building block that teno_rhs launches once per axis. */
+int teno_sweep(const teno_grid* g, int32_t axis, const double* U_dev,
+               const double* Rin_dev, double* Rout_dev, const double* alpha_dev,
+               void* stream);
+
+/* Self-test of the device arithmetic the path relies on, for n inputs:
+ * q[i] = a[i] / b[i] and s[i] = sqrt(a[i]), both correctly rounded (IEEE-754
+ * binary64, round to nearest even) whenever operands and results lie in
+ * [2^-900, 2^900] in magnitude (zero allowed for the numerator), and r[i]
+ * = the approximate reciprocal of b[i] used by the decision fast path.  All
+ * pointers are device pointers of n doubles. */
+int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
+                        double* s_dev, double* r_dev, int64_t n, void* stream);
+
+/* One SSP-RK3 step of eq 4.1-4.3, in place on U_dev:
+ *   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 u1 + 1/4 dt L(u1);
+ *   u  = 1/3 u + 2/3 u2 + 2/3 dt L(u2),
+ * with the LF speeds recomputed for every stage and dt from the speeds of u
+ * (eq dt1 in 1D, eq dt2 in 2D, sigma / sum_d(alpha_d / dx_d) in 3D), clipped
+ * so that t + dt <= t_end.  In replay mode (ctrl.replay = 1) dt and the
+ * per-stage speeds are read from the control block instead.  The step is a
+ * no-op when ctrl.status != OK or t >= t_end; a non-physical stage state sets
+ * ctrl.status and leaves U_dev at its value before the step. */
+int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
+              void* ws_dev, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TENO_H_ */

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libteno.so (include/teno.h).
+
+Argument marshalling only: every step of the numerical path runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensors) and the
+stream.  Loading fails loudly when the library has not been built; there is
+no CPU fallback.
+
+Fields are float64 CUDA tensors of shape (ndim + 2, nz, ny, nx) (unused axes
+of size 1), component order rho, rho*u_x, [rho*u_y], [rho*u_z], E.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libteno.so")
+
+OK, ERR_ARG, ERR_DEVICE, ERR_NONPHYSICAL = 0, 1, 2, 3
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2}
+
+
+class TenoGrid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("bc", ctypes.c_int32 * 3),
+        ("scheme", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("ct_fixed", ctypes.c_double),
+        ("H", ctypes.c_double),
+        ("Bl", ctypes.c_int32),
+        ("Bu", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("flags", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
+    ]
+
+
+FLAG_LITERAL_DECISIONS = 1
+
+
+class TenoCtrl(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double),
+        ("t_end", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("alpha", (ctypes.c_double * 3) * 3),
+        ("status", ctypes.c_int32),
+        ("replay", ctypes.c_int32),
+        ("nsteps", ctypes.c_int64),
+        ("active", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+CTRL_BYTES = ctypes.sizeof(TenoCtrl)
+assert CTRL_BYTES == 128
+
+# Every symbol declared in include/teno.h (checked by the ABI tests).
+SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_rhs", "teno_rhs_debug", "teno_sweep",
+           "teno_selftest_arith", "teno_step"]
+
+_lib = None
+
+
+class TenoError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libteno.so (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TenoError(f"{LIB_PATH} is missing: build it with "
+                            "`python paper_2003_09145_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        G = ctypes.POINTER(TenoGrid)
+        L.teno_workspace_bytes.argtypes = [G]
+        L.teno_workspace_bytes.restype = ctypes.c_size_t
+        L.teno_ctrl_init.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+        L.teno_ctrl_init.restype = ctypes.c_int
+        L.teno_rhs.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.teno_rhs.restype = ctypes.c_int
+        L.teno_rhs_debug.argtypes = [G, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.teno_rhs_debug.restype = ctypes.c_int
+        L.teno_sweep.argtypes = [G, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.teno_sweep.restype = ctypes.c_int
+        L.teno_selftest_arith.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+        L.teno_selftest_arith.restype = ctypes.c_int
+        L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
+        L.teno_step.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _get(prob, key, default=None):
+    if isinstance(prob, dict):
+        return prob.get(key, default)
+    return getattr(prob, key, default)
+
+
+def grid(prob) -> TenoGrid:
+    """teno_grid from a problem description (attributes or dict keys ndim, n,
+    dx, bc, gamma, scheme, ct_fixed, H, Bl, Bu, eps)."""
+    g = TenoGrid()
+    nd = int(_get(prob, "ndim"))
+    n = list(_get(prob, "n"))
+    dx = list(_get(prob, "dx"))
+    bc = _get(prob, "bc")
+    if isinstance(bc, (str, int)):
+        bc = [bc] * nd
+    g.ndim = nd
+    for k in range(3):
+        g.n[k] = int(n[k]) if k < nd else 1
+        g.dx[k] = float(dx[k]) if k < nd else 1.0
+        b = bc[k] if k < nd else 0
+        g.bc[k] = BC[b] if isinstance(b, str) else int(b)
+    sch = _get(prob, "scheme", "lad")
+    g.scheme = SCHEME[sch] if isinstance(sch, str) else int(sch)
+    g.gamma = float(_get(prob, "gamma", 1.4))
+    g.ct_fixed = float(_get(prob, "ct_fixed", 1e-7))
+    g.H = float(_get(prob, "H", 10.0))
+    g.Bl = int(_get(prob, "Bl", 4))
+    g.Bu = int(_get(prob, "Bu", 10))
+    g.eps = float(_get(prob, "eps", 1e-6))
+    g.flags = FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0
+    return g
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise TenoError(f"{what} failed with status {rc}")
+
+
+def workspace_bytes(g: TenoGrid) -> int:
+    return int(lib().teno_workspace_bytes(ctypes.byref(g)))
+
+
+def ctrl_init(ctrl, t0, t_end, cfl, stream=None):
+    _check(lib().teno_ctrl_init(_ptr(ctrl), float(t0), float(t_end), float(cfl), _stream(stream)),
+           "teno_ctrl_init")
+
+
+def teno_rhs(g, U, dUdt, ws, alpha_in=None, alpha_out=None, status=None, stream=None):
+    _check(lib().teno_rhs(ctypes.byref(g), _ptr(U), _ptr(dUdt), _ptr(alpha_in), _ptr(alpha_out),
+                          _ptr(status), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "teno_rhs")
+
+
+def teno_rhs_debug(g, U, dUdt, decisions, ws, alpha_in=None, alpha_out=None, status=None,
+                   stream=None):
+    _check(lib().teno_rhs_debug(ctypes.byref(g), _ptr(U), _ptr(dUdt), _ptr(alpha_in),
+                                _ptr(alpha_out), _ptr(status), _ptr(decisions), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)),
+           "teno_rhs_debug")
+
+
+def teno_sweep(g, axis, U, Rout, alpha, Rin=None, stream=None):
+    _check(lib().teno_sweep(ctypes.byref(g), int(axis), _ptr(U), _ptr(Rin), _ptr(Rout),
+                            _ptr(alpha), _stream(stream)), "teno_sweep")
+
+
+def selftest_arith(a, b, stream=None):
+    """(a / b, sqrt(a), approximate 1 / b) computed by the device."""
+    import torch
+    q, s, r = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    _check(lib().teno_selftest_arith(_ptr(a), _ptr(b), _ptr(q), _ptr(s), _ptr(r), a.numel(),
+                                     _stream(stream)), "teno_selftest_arith")
+    return q, s, r
+
+
+def teno_step(g, U, ctrl, ws, stream=None):
+    _check(lib().teno_step(ctypes.byref(g), _ptr(U), _ptr(ctrl), _ptr(ws),
+                           ws.numel() * ws.element_size(), _stream(stream)), "teno_step")
+
+
+def decisions_bytes(g: TenoGrid) -> int:
+    nc = g.ndim + 2
+    ncell = g.n[0] * g.n[1] * g.n[2]
+    return sum(ncell // g.n[d] * (g.n[d] + 1) * 2 * nc for d in range(g.ndim))
+
+
+class Solver:
+    """Owns the device workspace and control block of one grid."""
+
+    def __init__(self, prob, device="cuda"):
+        import torch
+        self.g = grid(prob)
+        nb = workspace_bytes(self.g)
+        if nb == 0:
+            raise TenoError("invalid grid")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.ctrl = torch.zeros(CTRL_BYTES, dtype=torch.uint8, device=self.device)
+        self.alpha = torch.zeros(3, dtype=torch.float64, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    def rhs(self, U, alpha_in=None, out=None, decisions=False):
+        import torch
+        out = torch.empty_like(U) if out is None else out
+        if decisions:
+            dec = torch.empty(decisions_bytes(self.g), dtype=torch.uint8, device=self.device)
+            teno_rhs_debug(self.g, U, out, dec, self.ws, alpha_in, self.alpha, self.status)
+            return out, dec
+        teno_rhs(self.g, U, out, self.ws, alpha_in, self.alpha, self.status)
+        return out
+
+    def init(self, t0=0.0, t_end=float("inf"), cfl=0.5):
+        ctrl_init(self.ctrl, t0, t_end, cfl)
+
+    def step(self, U):
+        teno_step(self.g, U, self.ctrl, self.ws)
+
+    def read_ctrl(self) -> TenoCtrl:
+        host = self.ctrl.cpu().numpy().tobytes()
+        return TenoCtrl.from_buffer_copy(host)
+
+    def write_ctrl(self, c: TenoCtrl):
+        import torch
+        buf = torch.frombuffer(bytearray(bytes(c)), dtype=torch.uint8)
+        self.ctrl.copy_(buf.to(self.device))

@@ -1,0 +1,288 @@
+// Device-side building blocks of the TENO5-LAD Euler right-hand side
+// (Peng et al., arXiv:2003.09145) for gfx950.
+//
+// Every function here evaluates its formula in one fixed operation order
+// (no FMA contraction: the library is built with -ffp-contract=off), so that
+// the GPU result is reproducible bit for bit and every cutoff decision is a
+// deterministic function of the input state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace teno {
+
+// Scheme parameters as the kernels see them (copied from teno_grid).
+struct SchemeParams {
+    double gamma;
+    double ct_fixed;
+    double H;
+    double eps;
+    int32_t scheme;  // 0 LAD, 1 fixed C_T, 2 linear (all stencils kept)
+    int32_t Bl, Bu;
+};
+
+// Ladder array of Sec. 3 eq 3.3 as decimal literals: kLadder[k] = 10^-k, so
+// C_T = Lad(m) = kLadder[m] (eq 3.4).
+__constant__ const double kLadder[21] = {
+    1e0,  1e-1,  1e-2,  1e-3,  1e-4,  1e-5,  1e-6,  1e-7,  1e-8,  1e-9, 1e-10,
+    1e-11, 1e-12, 1e-13, 1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
+
+// Coefficients of Sec. 2: the FP64 quotients of the printed integer ratios.
+constexpr double kB13_12 = 13.0 / 12.0;  // eq 2.9-2.11
+constexpr double kB1_4 = 0.25;
+constexpr double kC1_3 = 1.0 / 3.0;      // eq 2.4-2.6
+constexpr double kC7_6 = 7.0 / 6.0;
+constexpr double kC11_6 = 11.0 / 6.0;
+constexpr double kC1_6 = 1.0 / 6.0;
+constexpr double kC5_6 = 5.0 / 6.0;
+constexpr double kLin0 = 0.1, kLin1 = 0.6, kLin2 = 0.3;  // linear weights
+
+// ---------------------------------------------------------------------------
+// Correctly rounded FP64 division and square root.
+//
+// The compiler's FP64 a / b sequence on gfx950 is faithful but not always
+// correctly rounded (for instance 0.3499999999999998 / 0.12499999999999993
+// returns 2.8 instead of 2.8000000000000003), and the method's cutoff
+// decisions must match an IEEE-754 evaluation bit for bit.  Both wrappers take
+// the hardware result q (within one ulp), form the remainder with one FMA --
+// exact, because the remainder of a faithful quotient (a - q b) or root
+// (x - s^2) is representable -- and move q to its neighbour when the exact
+// value lies beyond the midpoint (ties to even for the quotient; a square
+// root of a double is never a midpoint).  Operands are restricted to
+// [2^-900, 2^900] in magnitude for the correction (no under/overflow in the
+// remainder); outside it the hardware value is returned.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double step_toward(double q, bool up) {
+    const long long bits = __double_as_longlong(q);
+    return __longlong_as_double(bits + (((q > 0.0) == up) ? 1ll : -1ll));
+}
+
+__device__ __forceinline__ bool in_safe_range(double v) {
+    const double av = fabs(v);
+    return av >= 0x1p-900 && av <= 0x1p900;
+}
+
+__device__ __forceinline__ double cr_div(double a, double b) {
+    const double q = a / b;
+    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return q;
+    const double r = __builtin_fma(-q, b, a);  // a - q b, exact
+    if (r == 0.0) return q;
+    const bool up = (r > 0.0) == (b > 0.0);     // true quotient above q
+    const double qn = step_toward(q, up);
+    const double h = 0.5 * ((qn - q) * b);      // remainder at the midpoint, exact
+    const double ar = fabs(r), ah = fabs(h);
+    if (ar > ah) return qn;
+    if (ar == ah) return (__double_as_longlong(q) & 1ll) ? qn : q;
+    return q;
+}
+
+__device__ __forceinline__ double cr_sqrt(double x) {
+    const double s = sqrt(x);
+    if (!(x >= 0x1p-900 && x <= 0x1p900)) return s;
+    const double r = __builtin_fma(-s, s, x);  // x - s^2, exact
+    if (r == 0.0) return s;
+    const bool up = r > 0.0;
+    const double sn = step_toward(s, up);
+    const double sg = s * (sn - s);             // exact: the gap is a power of two
+    if (up) return (r > sg) ? sn : s;
+    return (r <= sg) ? sn : s;
+}
+
+// Reciprocal to within a few ulp: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rcp_nr(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-b, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// TENO weights of eq 2.15 for each cutoff mask, omega_k = delta_k c_k / D with
+// D = (delta_0 c_0 + delta_1 c_1) + delta_2 c_2, folded at compile time in
+// IEEE round-to-nearest (the same operations and order as the runtime form).
+constexpr double omega_of(int mask, int k) {
+    const double d0 = (double)(mask & 1), d1 = (double)((mask >> 1) & 1),
+                 d2 = (double)((mask >> 2) & 1);
+    const double D = (d0 * 0.1 + d1 * 0.6) + d2 * 0.3;
+    const double dk = (k == 0) ? d0 : (k == 1) ? d1 : d2;
+    const double ck = (k == 0) ? 0.1 : (k == 1) ? 0.6 : 0.3;
+    return mask == 0 ? 0.0 : (dk * ck) / D;
+}
+__constant__ const double kOmega[8][3] = {
+    {omega_of(0, 0), omega_of(0, 1), omega_of(0, 2)},
+    {omega_of(1, 0), omega_of(1, 1), omega_of(1, 2)},
+    {omega_of(2, 0), omega_of(2, 1), omega_of(2, 2)},
+    {omega_of(3, 0), omega_of(3, 1), omega_of(3, 2)},
+    {omega_of(4, 0), omega_of(4, 1), omega_of(4, 2)},
+    {omega_of(5, 0), omega_of(5, 1), omega_of(5, 2)},
+    {omega_of(6, 0), omega_of(6, 1), omega_of(6, 2)},
+    {omega_of(7, 0), omega_of(7, 1), omega_of(7, 2)}};
+
+// Decision constants of one launch: LAD ladder thresholds on x = max_k
+// chi~_k.  For the literal mapping m(x) = B_l + floor(theta (B_u - B_l)),
+// theta = 1 / (1 + x / H) (every operation rounded to nearest), m(x) >= B_l + j
+// holds exactly for x <= xthr[j - 1]; the host finds each threshold by
+// bisection over the doubles of the literal formula.
+struct DecisionConsts {
+    double xthr[20];
+    int32_t nthr;       // B_u - B_l
+    int32_t literal;    // 1: evaluate every decision with the literal formula
+};
+
+// Relative margin inside which an approximate decision value is not trusted
+// (the approximate path differs from the literal one by < 200 ulp).
+constexpr double kDecisionMargin = 0x1p-40;
+
+// The literal decision of eq 2.8-2.14 / eq 3.1-3.4 (oracle operation order,
+// correctly rounded divisions).  Returns m | (mask << 5).
+__device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, double beta0,
+                                                      double beta1, double beta2) {
+    const double tau = fabs(beta2 - beta0);
+    const double t0 = cr_div(tau, beta0 + S.eps);
+    const double t1 = cr_div(tau, beta1 + S.eps);
+    const double t2 = cr_div(tau, beta2 + S.eps);
+    double y, y2;
+    y = 1.0 + t0;
+    y2 = y * y;
+    const double g0 = (y2 * y2) * y2;
+    y = 1.0 + t1;
+    y2 = y * y;
+    const double g1 = (y2 * y2) * y2;
+    y = 1.0 + t2;
+    y2 = y * y;
+    const double g2 = (y2 * y2) * y2;
+    const double sum = (g0 + g1) + g2;
+    const double chi0 = cr_div(g0, sum);
+    const double chi1 = cr_div(g1, sum);
+    const double chi2 = cr_div(g2, sum);
+    double ct = 0.0;
+    int m = 0;
+    if (S.scheme == 0) {
+        double x = t0;
+        if (t1 > x) x = t1;
+        if (t2 > x) x = t2;
+        const double theta = cr_div(1.0, 1.0 + cr_div(x, S.H));
+        if (theta >= 0.0)
+            m = S.Bl + (int)floor(theta * (double)(S.Bu - S.Bl));
+        else
+            m = S.Bl;
+        ct = kLadder[m];
+    } else {
+        ct = S.ct_fixed;
+    }
+    const uint32_t mask = (chi0 < ct ? 0u : 1u) | (chi1 < ct ? 0u : 2u) | (chi2 < ct ? 0u : 4u);
+    return (uint32_t)m | (mask << 5);
+}
+
+// One scalar TENO5 reconstruction of the face value from (a..e) =
+// (f_{i-2} .. f_{i+2}): smoothness indicators (eq 2.9-2.12), scale
+// separation (eq 2.8, 2.13), cutoff (eq 2.14) with C_T from the LAD mapping
+// (eq 3.1-3.4), weights (eq 2.15) and combination (eq 2.4-2.7).
+//
+// The cutoff flags and the ladder index are discrete functions of the
+// literal formula.  They are first evaluated with approximate reciprocals;
+// if any decision value lies within kDecisionMargin of its threshold (or is
+// not finite) the lane re-evaluates the literal formula, so the decisions
+// equal the literal ones exactly.  The flux itself is the literal
+// combination with the eq 2.15 weights of the chosen mask.
+// *code receives m | (mask << 5).
+__device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const DecisionConsts& K,
+                                                 double a, double b, double c, double d,
+                                                 double e, uint32_t* code) {
+    const double s01 = (a - 2.0 * b) + c;
+    const double s02 = (a - 4.0 * b) + 3.0 * c;
+    const double s11 = (b - 2.0 * c) + d;
+    const double s12 = b - d;
+    const double s21 = (c - 2.0 * d) + e;
+    const double s22 = (3.0 * c - 4.0 * d) + e;
+    const double beta0 = kB13_12 * (s01 * s01) + kB1_4 * (s02 * s02);
+    const double beta1 = kB13_12 * (s11 * s11) + kB1_4 * (s12 * s12);
+    const double beta2 = kB13_12 * (s21 * s21) + kB1_4 * (s22 * s22);
+
+    uint32_t cd;
+    if (S.scheme == 2) {
+        cd = 7u << 5;
+    } else {
+        bool sure = K.literal == 0;
+        uint32_t m = 0;
+        uint32_t mask = 7u;
+        if (sure) {
+            const double tau = fabs(beta2 - beta0);
+            const double t0 = tau * rcp_nr(beta0 + S.eps);
+            const double t1 = tau * rcp_nr(beta1 + S.eps);
+            const double t2 = tau * rcp_nr(beta2 + S.eps);
+            double y, y2;
+            y = 1.0 + t0;
+            y2 = y * y;
+            const double g0 = (y2 * y2) * y2;
+            y = 1.0 + t1;
+            y2 = y * y;
+            const double g1 = (y2 * y2) * y2;
+            y = 1.0 + t2;
+            y2 = y * y;
+            const double g2 = (y2 * y2) * y2;
+            const double sum = (g0 + g1) + g2;
+            const double rs = rcp_nr(sum);
+            const double chi0 = g0 * rs, chi1 = g1 * rs, chi2 = g2 * rs;
+            double ct;
+            if (S.scheme == 0) {
+                double x = t0;
+                if (t1 > x) x = t1;
+                if (t2 > x) x = t2;
+                sure = isfinite(x);
+                uint32_t above = 0;
+                for (int j = 0; j < K.nthr; ++j) {
+                    const double T = K.xthr[j];
+                    above += (x <= T) ? 1u : 0u;
+                    sure = sure && (fabs(x - T) > kDecisionMargin * T);
+                }
+                m = (uint32_t)S.Bl + above;
+                ct = kLadder[m];
+            } else {
+                ct = S.ct_fixed;
+            }
+            const double band = kDecisionMargin * ct;
+            sure = sure && isfinite(sum) && fabs(chi0 - ct) > band && fabs(chi1 - ct) > band &&
+                   fabs(chi2 - ct) > band;
+            mask = (chi0 < ct ? 0u : 1u) | (chi1 < ct ? 0u : 2u) | (chi2 < ct ? 0u : 4u);
+        }
+        cd = m | (mask << 5);
+        if (!sure) cd = teno5_decide_literal(S, beta0, beta1, beta2);
+    }
+    *code = cd;
+    const uint32_t mask = cd >> 5;
+    const double f0 = (kC1_3 * a - kC7_6 * b) + kC11_6 * c;
+    const double f1 = (-kC1_6 * b + kC5_6 * c) + kC1_3 * d;
+    const double f2 = (kC1_3 * c + kC5_6 * d) - kC1_6 * e;
+    return (kOmega[mask][0] * f0 + kOmega[mask][1] * f1) + kOmega[mask][2] * f2;
+}
+
+// Ghost-cell source along a swept axis: periodic wrap, zero-gradient copy or
+// reflecting mirror (normal momentum negated), three cells per side.
+__device__ __forceinline__ int ghost_src(int bc, int n, int j, bool* flip) {
+    *flip = false;
+    if (j >= 0 && j < n) return j;
+    if (bc == 0) return j < 0 ? j + n : j - n;  // |j| <= 3 <= n
+    if (bc == 1) return j < 0 ? 0 : n - 1;
+    *flip = true;
+    return j < 0 ? -1 - j : 2 * n - 1 - j;
+}
+
+// Local component order of a sweep along DIR: rho, normal momentum, the
+// tangential momenta in increasing axis order, E.
+template <int ND, int DIR>
+struct LocalOrder {
+    static constexpr int NC = ND + 2;
+    __device__ static constexpr int nat(int q) {
+        // q = 0 -> 0; q = 1 -> 1 + DIR; q = 2..ND -> tangential axes; q = NC-1 -> NC-1
+        return q == 0 ? 0
+               : q == 1 ? 1 + DIR
+               : q == NC - 1 ? NC - 1
+               : 1 + ((q - 2) < DIR ? (q - 2) : (q - 1));
+    }
+    // tangential axis index of local tangential slot k = 1 .. ND-1
+    __device__ static constexpr int tan_axis(int k) { return (k - 1) < DIR ? (k - 1) : k; }
+};
+
+}  // namespace teno

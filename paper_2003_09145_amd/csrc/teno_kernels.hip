@@ -1,0 +1,721 @@
+// HIP kernels of the TENO5-LAD Euler right-hand side for gfx950 and the
+// C-ABI entry points declared in include/teno.h.
+//
+// Sweep design ("face stream"): for one axis the lines along that axis are
+// concatenated into one flat sequence of faces, n + 1 faces per line.  Each
+// 64-lane wave takes 64 consecutive faces of that sequence, starting at a
+// multiple of 63, so consecutive waves overlap by one face: lane l computes
+// the numerical flux at its face, and lanes 1..63 difference their face with
+// the previous lane's to update one cell each.  Every cell is updated by
+// exactly one lane, with no idle lanes in the interior of the sequence and no
+// tile-edge raggedness for any line length (the one face in 64 computed
+// twice is the only redundancy).  The per-cell quantities that all six faces
+// around a cell need (split fluxes in local order, sqrt(rho), u, H) are
+// computed once per cell into LDS and read back by the faces.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+#include <string.h>
+
+#include "../../include/teno.h"
+#include "teno_device.hpp"
+
+namespace teno {
+
+constexpr int kMaxLdsPerBlock = 64 * 1024;
+constexpr int kFacesPerChunk = 64;
+constexpr int kCellsPerChunk = 63;
+
+// Per-launch description of one sweep.
+struct SweepArgs {
+    const double* U;        // state the stencils read (stage input)
+    const double* Rin;      // partial RHS of earlier axes (nullable: start from 0)
+    double* Rout;           // RHS output (rk == 0)
+    const double* Un;       // u^n (rk == 2, 3)
+    double* Uout;           // RK stage output (rk > 0)
+    const double* alpha;    // LF speeds, 3 doubles (indexed by axis)
+    const teno_ctrl* ctrl;  // nullable: gating and dt
+    uint8_t* dump;          // nullable: decision bytes of this axis
+    int64_t ncell;
+    int64_t line_step;      // cell-index step between consecutive lines of a column
+    int64_t stride;         // cell-index step along the swept axis
+    int64_t col_step;       // cell-index step between columns
+    int64_t ftot;           // faces per column = lines_per_col * (n + 1)
+    int64_t nchunks;        // chunks per column * ncols
+    int64_t ncols;
+    int32_t n;              // cells along the swept axis
+    int32_t bc;
+    int32_t rk;             // 0: write RHS; 1..3: fused RK stage
+    int32_t ext_cap;        // LDS ext cells per wave
+    double dx;
+    SchemeParams sch;
+    DecisionConsts dk;
+};
+
+// Map the hardware block index to a logical index such that blocks that run
+// on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
+// logical indices, so neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+template <int ND, int DIR, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
+    constexpr int NC = ND + 2;
+    constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
+    using LO = LocalOrder<ND, DIR>;
+    extern __shared__ double smem[];
+
+    if (A.ctrl != nullptr) {
+        if (!A.ctrl->active || A.ctrl->status != 0) return;  // uniform across the grid
+    }
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t chunk = lb * W + wave;
+    const bool wave_ok = chunk < A.nchunks;
+    const int n = A.n;
+    const int64_t np1 = n + 1, np6 = n + 6;
+    int64_t col = 0, k = chunk;
+    if (DIR != 0) {  // columns fastest: neighbouring waves read neighbouring x
+        col = chunk % A.ncols;
+        k = chunk / A.ncols;
+    }
+    const int64_t colbase = col * A.col_step;
+    const int cap = A.ext_cap;
+    double* ext = smem + (size_t)wave * (cap * NV + 64 * NC);
+    double* fhs = ext + (size_t)cap * NV;
+
+    const int64_t F0 = k * kCellsPerChunk;
+    const int64_t F = F0 + lane;
+    const bool valid = wave_ok && F < A.ftot;
+    const int64_t Fc = valid ? F : F0;
+    const int64_t bl = Fc / np1;            // line of this lane's face
+    const int64_t phi = Fc - bl * np1;      // face index in the line (i + 1)
+    const int64_t e_lo = F0 + 5 * (F0 / np1);
+    int64_t Flast = F0 + 63;
+    if (Flast > A.ftot - 1) Flast = A.ftot - 1;
+    const int64_t e_hi = Flast + 5 * (Flast / np1) + 6;
+    const int count = wave_ok ? (int)(e_hi - e_lo) : 0;
+
+    // ---- stage per-cell quantities of the ext cells [e_lo, e_hi) ----------
+    const double alpha = A.alpha[DIR];
+    const double gm1 = A.sch.gamma - 1.0;
+    for (int idx = lane; idx < count; idx += 64) {
+        const int64_t e = e_lo + idx;
+        const int64_t b = e / np6;
+        const int j = (int)(e - b * np6) - 3;
+        bool flip;
+        const int src = ghost_src(A.bc, n, j, &flip);
+        const int64_t cell = colbase + b * A.line_step + (int64_t)src * A.stride;
+        double q[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
+        if (flip) q[1 + DIR] = -q[1 + DIR];
+        // primitives (natural order), as u_k = m_k / rho, p = (gamma-1)(E - ke)
+        const double rho = q[0];
+        double u[ND];
+#pragma unroll
+        for (int kk = 0; kk < ND; ++kk) u[kk] = cr_div(q[1 + kk], rho);
+        double mu = q[1] * u[0];
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) mu = mu + q[1 + kk] * u[kk];
+        const double ke = 0.5 * mu;
+        const double E = q[NC - 1];
+        const double p = gm1 * (E - ke);
+        const double H = cr_div(E + p, rho);
+        // flux along DIR (natural order)
+        double Fl[NC];
+        Fl[0] = q[1 + DIR];
+#pragma unroll
+        for (int kk = 0; kk < ND; ++kk)
+            Fl[1 + kk] = (kk == DIR) ? q[1 + kk] * u[DIR] + p : q[1 + kk] * u[DIR];
+        Fl[NC - 1] = (E + p) * u[DIR];
+        // global Lax-Friedrichs split in local order
+#pragma unroll
+        for (int qq = 0; qq < NC; ++qq) {
+            const int g = LO::nat(qq);
+            ext[(size_t)qq * cap + idx] = 0.5 * (Fl[g] + alpha * q[g]);
+            ext[(size_t)(NC + qq) * cap + idx] = 0.5 * (Fl[g] - alpha * q[g]);
+        }
+        ext[(size_t)(2 * NC) * cap + idx] = cr_sqrt(rho);
+#pragma unroll
+        for (int kk = 0; kk < ND; ++kk) ext[(size_t)(2 * NC + 1 + kk) * cap + idx] = u[kk];
+        ext[(size_t)(2 * NC + 1 + ND) * cap + idx] = H;
+    }
+    __syncthreads();
+
+    // ---- numerical flux at this lane's face ----------------------------------
+    if (valid) {
+        const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of cell i-2
+        const double* sr = ext + (size_t)(2 * NC) * cap;
+        const double* uu = ext + (size_t)(2 * NC + 1) * cap;
+        const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
+        // Roe average of cells i (o+2) and i+1 (o+3)
+        const double rl = sr[o + 2], rr = sr[o + 3];
+        const double wsum = cr_div(1.0, rl + rr);
+        double ub[ND];
+#pragma unroll
+        for (int kk = 0; kk < ND; ++kk)
+            ub[kk] = (rl * uu[(size_t)kk * cap + o + 2] + rr * uu[(size_t)kk * cap + o + 3]) * wsum;
+        const double Hb = (rl * hh[o + 2] + rr * hh[o + 3]) * wsum;
+        double q2 = ub[0] * ub[0];
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) q2 = q2 + ub[kk] * ub[kk];
+        const double c2 = gm1 * (Hb - 0.5 * q2);
+        const double cs = cr_sqrt(c2);
+        const double ci = cr_div(1.0, cs);
+        const double b1 = cr_div(gm1, c2);
+        const double b2 = (0.5 * q2) * b1;
+        const double un = ub[DIR];
+        double ut[ND > 1 ? ND - 1 : 1];
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) ut[kk - 1] = ub[LO::tan_axis(kk)];
+
+        double Fh[NC];  // local order accumulators of R * fhat
+        uint32_t codes[2 * NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            // left eigenvector row s (local order)
+            double Lr[NC];
+            if (s == 0 || s == NC - 1) {
+                const double sg = (s == 0) ? 1.0 : -1.0;
+                Lr[0] = (s == 0) ? 0.5 * (b2 + un * ci) : 0.5 * (b2 - un * ci);
+                Lr[1] = (s == 0) ? 0.5 * (-(b1 * un) - ci) : 0.5 * (-(b1 * un) + ci);
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-(b1 * ut[kk - 1]));
+                Lr[NC - 1] = 0.5 * b1;
+                (void)sg;
+            } else if (s == 1) {
+                Lr[0] = 1.0 - b2;
+                Lr[1] = b1 * un;
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = b1 * ut[kk - 1];
+                Lr[NC - 1] = -b1;
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < NC; ++qq) Lr[qq] = 0.0;
+                Lr[0] = -ut[s - 2];
+            }
+            // project the split fluxes of the six stencil cells
+            double vp[5], vm[5];
+#pragma unroll
+            for (int jj = 0; jj < 6; ++jj) {
+                const int idx = o + jj;
+                double ap = 0.0, am = 0.0;
+                if (s == 0 || s == 1 || s == NC - 1) {
+                    ap = Lr[0] * ext[idx];
+                    am = Lr[0] * ext[(size_t)NC * cap + idx];
+#pragma unroll
+                    for (int qq = 1; qq < NC; ++qq) {
+                        ap = ap + Lr[qq] * ext[(size_t)qq * cap + idx];
+                        am = am + Lr[qq] * ext[(size_t)(NC + qq) * cap + idx];
+                    }
+                } else {  // shear row: -u_t f_rho + f_{m_t}
+                    ap = Lr[0] * ext[idx] + ext[(size_t)(s) * cap + idx];
+                    am = Lr[0] * ext[(size_t)NC * cap + idx] + ext[(size_t)(NC + s) * cap + idx];
+                }
+                if (jj < 5) vp[jj] = ap;
+                if (jj > 0) vm[jj - 1] = am;
+            }
+            uint32_t cp, cm;
+            const double rp = teno5_rec_fast(A.sch, A.dk, vp[0], vp[1], vp[2], vp[3], vp[4], &cp);
+            const double rm = teno5_rec_fast(A.sch, A.dk, vm[4], vm[3], vm[2], vm[1], vm[0], &cm);
+            codes[2 * s] = cp;
+            codes[2 * s + 1] = cm;
+            const double fh = rp + rm;
+            // accumulate R[:, s] * fh in local order
+            if (s == 0) {
+                Fh[0] = fh;
+                Fh[1] = (un - cs) * fh;
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = ut[kk - 1] * fh;
+                Fh[NC - 1] = (Hb - un * cs) * fh;
+            } else if (s == 1) {
+                Fh[0] = Fh[0] + fh;
+                Fh[1] = Fh[1] + un * fh;
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
+                Fh[NC - 1] = Fh[NC - 1] + (0.5 * q2) * fh;
+            } else if (s == NC - 1) {
+                Fh[0] = Fh[0] + fh;
+                Fh[1] = Fh[1] + (un + cs) * fh;
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
+                Fh[NC - 1] = Fh[NC - 1] + (Hb + un * cs) * fh;
+            } else {
+                Fh[s] = Fh[s] + fh;  // local slot s is tangential s - 1
+                Fh[NC - 1] = Fh[NC - 1] + ut[s - 2] * fh;
+            }
+        }
+#pragma unroll
+        for (int qq = 0; qq < NC; ++qq) fhs[LO::nat(qq) * 64 + lane] = Fh[qq];
+        if (A.dump != nullptr) {
+            // oracle line numbering: x: k*ny + j; y: k*nx + i; z: j*nx + i
+            const int64_t gline = (DIR == 0) ? bl : bl * A.ncols + col;
+            uint8_t* o8 = A.dump + (gline * np1 + phi) * (2 * NC);
+#pragma unroll
+            for (int kk = 0; kk < 2 * NC; ++kk) o8[kk] = (uint8_t)codes[kk];
+        }
+    }
+    __syncthreads();
+
+    // ---- flux difference and epilogue ---------------------------------------
+    if (valid && lane > 0 && phi > 0) {
+        const int64_t cell = colbase + bl * A.line_step + (phi - 1) * A.stride;
+        double r[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double diff = fhs[c * 64 + lane] - fhs[c * 64 + lane - 1];
+            const double prev = (A.Rin != nullptr) ? A.Rin[c * A.ncell + cell] : 0.0;
+            r[c] = prev - cr_div(diff, A.dx);
+        }
+        if (A.rk == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) A.Rout[c * A.ncell + cell] = r[c];
+        } else {
+            const double h = A.ctrl->dt;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const size_t at = (size_t)c * A.ncell + cell;
+                double v;
+                if (A.rk == 1) {
+                    v = A.U[at] + h * r[c];
+                } else if (A.rk == 2) {
+                    v = (0.75 * A.Un[at] + 0.25 * A.U[at]) + 0.25 * (h * r[c]);
+                } else {
+                    v = ((1.0 / 3.0) * A.Un[at] + (2.0 / 3.0) * A.U[at]) + (2.0 / 3.0) * (h * r[c]);
+                }
+                A.Uout[at] = v;
+            }
+        }
+    }
+}
+
+// ---- global Lax-Friedrichs speeds: alpha_d = max (|u_d| + c) -------------
+template <int ND>
+__global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ U, int64_t ncell,
+                                               double gamma,
+                                               unsigned long long* __restrict__ abits,
+                                               int32_t* __restrict__ status) {
+    constexpr int NC = ND + 2;
+    double amax[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) amax[k] = 0.0;
+    bool bad = false;
+    const double gm1 = gamma - 1.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double q[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = U[c * ncell + i];
+        const double rho = q[0];
+        double u[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) u[k] = cr_div(q[1 + k], rho);
+        double mu = q[1] * u[0];
+#pragma unroll
+        for (int k = 1; k < ND; ++k) mu = mu + q[1 + k] * u[k];
+        const double ke = 0.5 * mu;
+        const double p = gm1 * (q[NC - 1] - ke);
+        const double cs = cr_sqrt(cr_div(gamma * p, rho));
+        if (!(rho > 0.0) || !(p > 0.0) || !isfinite(cs)) bad = true;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            const double s = fabs(u[k]) + cs;
+            if (s > amax[k]) amax[k] = s;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        double v = amax[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, 64);
+            if (o > v) v = o;
+        }
+        if ((threadIdx.x & 63) == 0 && v > 0.0)
+            atomicMax(&abits[k], (unsigned long long)__double_as_longlong(v));
+    }
+    if (bad && status != nullptr) atomicMax(status, (int32_t)TENO_ERR_NONPHYSICAL);
+}
+
+__global__ void k_zero_scratch(unsigned long long* abits, int32_t* status) {
+    if (threadIdx.x < 3) abits[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0 && status != nullptr) *status = 0;
+}
+
+__global__ void k_copy_alpha(const unsigned long long* abits, const double* alpha_in,
+                             double* alpha_used, double* alpha_out) {
+    const int k = threadIdx.x;
+    if (k < 3) {
+        const double a = alpha_in ? alpha_in[k] : __longlong_as_double((long long)abits[k]);
+        alpha_used[k] = a;
+        if (alpha_out) alpha_out[k] = a;
+    }
+}
+
+// Stage bookkeeping of teno_step (one thread).
+__global__ void k_stage_begin(teno_ctrl* ctrl, const unsigned long long* abits, int stage,
+                              int ndim, double dx0, double dx1, double dx2) {
+    if (threadIdx.x != 0) return;
+    if (stage == 0) {
+        ctrl->active = 0;
+        if (ctrl->status != 0 || !(ctrl->t < ctrl->t_end)) return;
+        if (!ctrl->replay) {
+            double a[3];
+            for (int k = 0; k < 3; ++k) a[k] = __longlong_as_double((long long)abits[k]);
+            double dt;
+            if (ndim == 1) {
+                dt = cr_div(ctrl->cfl * dx0, a[0]);
+            } else if (ndim == 2) {
+                const double dtx = cr_div(dx0, a[0]);
+                const double dty = cr_div(dx1, a[1]);
+                dt = cr_div(ctrl->cfl * (dtx * dty), dtx + dty);
+            } else {
+                dt = cr_div(ctrl->cfl, (cr_div(a[0], dx0) + cr_div(a[1], dx1)) + cr_div(a[2], dx2));
+            }
+            if (ctrl->t + dt > ctrl->t_end) dt = ctrl->t_end - ctrl->t;
+            ctrl->dt = dt;
+            for (int k = 0; k < 3; ++k) ctrl->alpha[0][k] = a[k];
+        }
+        ctrl->active = 1;
+    } else {
+        if (!ctrl->active) return;
+        if (ctrl->status != 0) {
+            ctrl->active = 0;
+            return;
+        }
+        if (!ctrl->replay)
+            for (int k = 0; k < 3; ++k)
+                ctrl->alpha[stage][k] = __longlong_as_double((long long)abits[k]);
+    }
+}
+
+__global__ void k_step_end(teno_ctrl* ctrl) {
+    if (threadIdx.x != 0) return;
+    if (ctrl->active && ctrl->status == 0) {
+        ctrl->t = ctrl->t + ctrl->dt;
+        ctrl->nsteps += 1;
+    }
+    ctrl->active = 0;
+}
+
+__global__ void k_ctrl_init(teno_ctrl* ctrl, double t0, double t_end, double cfl) {
+    if (threadIdx.x != 0) return;
+    ctrl->t = t0;
+    ctrl->t_end = t_end;
+    ctrl->cfl = cfl;
+    ctrl->dt = 0.0;
+    for (int s = 0; s < 3; ++s)
+        for (int k = 0; k < 3; ++k) ctrl->alpha[s][k] = 0.0;
+    ctrl->status = 0;
+    ctrl->replay = 0;
+    ctrl->nsteps = 0;
+    ctrl->active = 0;
+    ctrl->pad_ = 0;
+}
+
+// Arithmetic self-test: the device's correctly rounded division and square
+// root and the approximate reciprocal used by the decision fast path.
+__global__ void k_selftest_arith(const double* a, const double* b, double* q, double* s,
+                                 double* r, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        q[i] = cr_div(a[i], b[i]);
+        s[i] = cr_sqrt(a[i]);
+        r[i] = rcp_nr(b[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct Scratch {  // small device area at the end of the workspace
+    unsigned long long abits[4];
+    double alpha_used[4];
+    int32_t status;
+    int32_t pad[7];
+};
+
+static int validate(const teno_grid* g) {
+    if (g == nullptr) return TENO_ERR_ARG;
+    if (g->ndim < 1 || g->ndim > 3) return TENO_ERR_ARG;
+    for (int k = 0; k < 3; ++k) {
+        if (k < g->ndim) {
+            if (g->n[k] < 3) return TENO_ERR_ARG;
+            if (!(g->dx[k] > 0.0)) return TENO_ERR_ARG;
+            if (g->bc[k] < 0 || g->bc[k] > 2) return TENO_ERR_ARG;
+        } else if (g->n[k] != 1) {
+            return TENO_ERR_ARG;
+        }
+    }
+    if (!(g->gamma > 1.0)) return TENO_ERR_ARG;
+    if (g->scheme < 0 || g->scheme > 2) return TENO_ERR_ARG;
+    if (g->scheme == 0) {
+        if (g->Bl < 0 || g->Bu > 20 || g->Bl > g->Bu || !(g->H > 0.0)) return TENO_ERR_ARG;
+    }
+    if (!(g->eps > 0.0)) return TENO_ERR_ARG;
+    if (g->flags & ~TENO_FLAG_LITERAL_DECISIONS) return TENO_ERR_ARG;
+    return TENO_OK;
+}
+
+static int64_t ncell_of(const teno_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
+
+static size_t state_bytes(const teno_grid* g) {
+    return (size_t)(g->ndim + 2) * (size_t)ncell_of(g) * sizeof(double);
+}
+
+static size_t workspace_bytes_impl(const teno_grid* g) {
+    return 3 * state_bytes(g) + sizeof(Scratch) + 256;
+}
+
+static Scratch* scratch_of(const teno_grid* g, void* ws) {
+    return (Scratch*)((char*)ws + 3 * state_bytes(g));
+}
+
+static SchemeParams scheme_of(const teno_grid* g) {
+    SchemeParams s;
+    s.gamma = g->gamma;
+    s.ct_fixed = g->ct_fixed;
+    s.H = g->H;
+    s.eps = g->eps;
+    s.scheme = g->scheme;
+    s.Bl = g->Bl;
+    s.Bu = g->Bu;
+    return s;
+}
+
+static int ext_cap_for(int n) { return 69 + 5 * (63 / (n + 1) + 1); }
+
+// The literal LAD ladder index of eq 3.1-3.2 evaluated on the host (IEEE
+// binary64, round to nearest): m(x) = B_l + floor(theta (B_u - B_l)),
+// theta = 1 / (1 + x / H).
+static int lad_m_host(double x, double H, int Bl, int Bu) {
+    const double theta = 1.0 / (1.0 + x / H);
+    if (theta >= 0.0) return Bl + (int)floor(theta * (double)(Bu - Bl));
+    return Bl;
+}
+
+// m(x) is non-increasing in x >= 0 (every operation is monotone), so for each
+// j = 1 .. B_u - B_l the set {x : m(x) >= B_l + j} is [0, X_j]; X_j is found
+// by bisection over the bit patterns of the non-negative doubles.
+static DecisionConsts decision_consts(const teno_grid* g) {
+    DecisionConsts K;
+    memset(&K, 0, sizeof(K));
+    K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
+    if (g->scheme != TENO_SCHEME_LAD) return K;
+    K.nthr = g->Bu - g->Bl;
+    for (int j = 1; j <= K.nthr; ++j) {
+        uint64_t lo = 0, hi = 0x7ff0000000000000ull;  // m(0) = B_u, m(inf) = B_l
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            double x;
+            memcpy(&x, &mid, sizeof(x));
+            if (lad_m_host(x, g->H, g->Bl, g->Bu) >= g->Bl + j)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        memcpy(&K.xthr[j - 1], &lo, sizeof(double));
+    }
+    return K;
+}
+
+template <int ND, int DIR>
+static hipError_t launch_sweep_t(SweepArgs A, hipStream_t st) {
+    constexpr int NC = ND + 2;
+    constexpr int NV = 2 * NC + ND + 2;
+    const size_t per_wave = (size_t)(A.ext_cap * NV + 64 * NC) * sizeof(double);
+    if (4 * per_wave <= (size_t)kMaxLdsPerBlock) {
+        const int64_t blocks = (A.nchunks + 3) / 4;
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 4>), dim3((unsigned)blocks), dim3(256), 4 * per_wave, st, A);
+    } else {
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 1>), dim3((unsigned)A.nchunks), dim3(64), per_wave, st, A);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStream_t st) {
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int n = g->n[dir];
+    A.n = n;
+    A.bc = g->bc[dir];
+    A.dx = g->dx[dir];
+    A.ncell = ncell_of(g);
+    A.sch = scheme_of(g);
+    A.dk = decision_consts(g);
+    A.ext_cap = ext_cap_for(n);
+    int64_t lines_per_col;
+    if (dir == 0) {
+        A.ncols = 1;
+        A.col_step = 0;
+        A.line_step = nx;
+        A.stride = 1;
+        lines_per_col = (int64_t)ny * nz;
+    } else if (dir == 1) {
+        A.ncols = nx;
+        A.col_step = 1;
+        A.line_step = (int64_t)nx * ny;
+        A.stride = nx;
+        lines_per_col = nz;
+    } else {
+        A.ncols = nx;
+        A.col_step = 1;
+        A.line_step = nx;
+        A.stride = (int64_t)nx * ny;
+        lines_per_col = ny;
+    }
+    A.ftot = lines_per_col * (n + 1);
+    const int64_t chunks_per_col = (A.ftot - 1 + kCellsPerChunk - 1) / kCellsPerChunk;
+    A.nchunks = chunks_per_col * A.ncols;
+    switch (g->ndim * 4 + dir) {
+        case 4: return launch_sweep_t<1, 0>(A, st);
+        case 8: return launch_sweep_t<2, 0>(A, st);
+        case 9: return launch_sweep_t<2, 1>(A, st);
+        case 12: return launch_sweep_t<3, 0>(A, st);
+        case 13: return launch_sweep_t<3, 1>(A, st);
+        case 14: return launch_sweep_t<3, 2>(A, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_alpha(const teno_grid* g, const double* U, unsigned long long* abits,
+                               int32_t* status, hipStream_t st) {
+    const int64_t nc = ncell_of(g);
+    int64_t blocks = (nc + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    switch (g->ndim) {
+        case 1: hipLaunchKernelGGL(k_alpha<1>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
+        case 2: hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
+        case 3: hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
+    }
+    return hipGetLastError();
+}
+
+static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
+                      double* alpha_out, int32_t* status, uint8_t* dump, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (validate(g) != TENO_OK || U == nullptr || dUdt == nullptr || ws == nullptr ||
+        ws_bytes < workspace_bytes_impl(g))
+        return TENO_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch* S = scratch_of(g, ws);
+    hipLaunchKernelGGL(k_zero_scratch, dim3(1), dim3(64), 0, st, S->abits, status);
+    if (alpha_in == nullptr) {
+        if (launch_alpha(g, U, S->abits, status, st) != hipSuccess) return TENO_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_copy_alpha, dim3(1), dim3(64), 0, st, S->abits, alpha_in,
+                       S->alpha_used, alpha_out);
+    int64_t dump_off = 0;
+    for (int d = 0; d < g->ndim; ++d) {
+        SweepArgs A;
+        memset(&A, 0, sizeof(A));
+        A.U = U;
+        A.Rin = (d == 0) ? nullptr : dUdt;
+        A.Rout = dUdt;
+        A.alpha = S->alpha_used;
+        A.dump = dump ? dump + dump_off : nullptr;
+        A.rk = 0;
+        if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;
+        dump_off += ncell_of(g) / g->n[d] * (int64_t)(g->n[d] + 1) * 2 * (g->ndim + 2);
+    }
+    return TENO_OK;
+}
+
+}  // namespace teno
+
+using namespace teno;
+
+extern "C" {
+
+size_t teno_workspace_bytes(const teno_grid* g) {
+    if (validate(g) != TENO_OK) return 0;
+    return workspace_bytes_impl(g);
+}
+
+int teno_ctrl_init(teno_ctrl* ctrl, double t0, double t_end, double cfl, void* stream) {
+    if (ctrl == nullptr || !(cfl > 0.0)) return TENO_ERR_ARG;
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, (hipStream_t)stream, ctrl, t0, t_end, cfl);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+int teno_rhs(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
+             double* alpha_out, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    return rhs_common(g, U, dUdt, alpha_in, alpha_out, status, nullptr, ws, ws_bytes, stream);
+}
+
+int teno_rhs_debug(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
+                   double* alpha_out, int32_t* status, uint8_t* decisions, void* ws,
+                   size_t ws_bytes, void* stream) {
+    if (decisions == nullptr) return TENO_ERR_ARG;
+    return rhs_common(g, U, dUdt, alpha_in, alpha_out, status, decisions, ws, ws_bytes, stream);
+}
+
+int teno_selftest_arith(const double* a, const double* b, double* q, double* s, double* r,
+                        int64_t n, void* stream) {
+    if (n < 0 || (n > 0 && (a == nullptr || b == nullptr || q == nullptr || s == nullptr ||
+                            r == nullptr)))
+        return TENO_ERR_ARG;
+    if (n == 0) return TENO_OK;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_selftest_arith, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, a, b, q, s, r, n);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+int teno_sweep(const teno_grid* g, int32_t axis, const double* U, const double* Rin,
+               double* Rout, const double* alpha, void* stream) {
+    if (validate(g) != TENO_OK || axis < 0 || axis >= g->ndim || U == nullptr ||
+        Rout == nullptr || alpha == nullptr)
+        return TENO_ERR_ARG;
+    SweepArgs A;
+    memset(&A, 0, sizeof(A));
+    A.U = U;
+    A.Rin = Rin;
+    A.Rout = Rout;
+    A.alpha = alpha;
+    return launch_sweep(g, axis, A, (hipStream_t)stream) == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
+              void* stream) {
+    if (validate(g) != TENO_OK || U == nullptr || ctrl == nullptr || ws == nullptr ||
+        ws_bytes < workspace_bytes_impl(g))
+        return TENO_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t sb = state_bytes(g);
+    double* R = (double*)ws;
+    double* U1 = (double*)((char*)ws + sb);
+    double* U2 = (double*)((char*)ws + 2 * sb);
+    Scratch* S = scratch_of(g, ws);
+    const double* stage_in[3] = {U, U1, U2};
+    double* stage_out[3] = {U1, U2, U};
+    for (int s = 0; s < 3; ++s) {
+        hipLaunchKernelGGL(k_zero_scratch, dim3(1), dim3(64), 0, st, S->abits, (int32_t*)nullptr);
+        if (launch_alpha(g, stage_in[s], S->abits, &ctrl->status, st) != hipSuccess)
+            return TENO_ERR_DEVICE;
+        hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(64), 0, st, ctrl, S->abits, s, g->ndim,
+                           g->dx[0], g->dx[1], g->dx[2]);
+        for (int d = 0; d < g->ndim; ++d) {
+            SweepArgs A;
+            memset(&A, 0, sizeof(A));
+            A.U = stage_in[s];
+            A.Rin = (d == 0) ? nullptr : R;
+            A.Rout = R;
+            A.alpha = &ctrl->alpha[s][0];
+            A.ctrl = ctrl;
+            if (d == g->ndim - 1) {
+                A.rk = s + 1;
+                A.Un = U;
+                A.Uout = stage_out[s];
+            }
+            if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;
+        }
+    }
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctrl);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bar (per RHS evaluation): every cutoff decision identical (flips counted and
+required to be zero) and, per component, max |RHS_gpu - RHS_oracle| /
+max |RHS_oracle| <= 1e-12.  The library is built without FMA contraction and
+evaluates the oracle's operation order, so the RHS is in fact expected to be
+bit-identical; that is asserted separately.
+"""
+import numpy as np
+import pytest
+
+from paper_2003_09145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2003_09145_amd import binding
+    binding.lib()
+    return binding
+
+
+def _gpu_rhs(torch, B, prob, U, alpha=None):
+    S = B.Solver(prob)
+    Ud = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    a = None if alpha is None else torch.from_numpy(np.asarray(alpha, dtype=np.float64)).cuda()
+    out, dec = S.rhs(Ud, alpha_in=a, decisions=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), dec.cpu().numpy(), S.alpha.cpu().numpy(), int(S.status.cpu()[0])
+
+
+def compare(Rg, Rc, dg, dc, label=""):
+    flips = int(np.count_nonzero(dg != dc))
+    mflips = int(np.count_nonzero((dg & 31) != (dc & 31)))
+    kflips = int(np.count_nonzero((dg >> 5) != (dc >> 5)))
+    nc = Rc.shape[0]
+    scale = np.abs(Rc).reshape(nc, -1).max(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    rel = (np.abs(Rg - Rc).reshape(nc, -1).max(axis=1) / scale).max()
+    bitwise = bool(np.array_equal(Rg, Rc))
+    print(f"[parity] {label}: flips={flips} (m {mflips}, mask {kflips}) max_rel={rel:.3e} "
+          f"bitwise={bitwise}", flush=True)
+    return flips, rel, bitwise
+
+
+CASES = {
+    "1d_sod200": lambda: W.sod(200),
+    "1d_shu_osher400": lambda: W.shu_osher(400),
+    "1d_blast400_reflective": lambda: W.blast_waves(400),
+    "1d_random131_reflective": lambda: (lambda p: (p, W.random_field(p, seed=4)))(
+        W.uniform_problem(1, [131], [0.0], [1.0], "reflective")),
+    "1d_random3_periodic": lambda: (lambda p: (p, W.random_field(p, seed=5)))(
+        W.uniform_problem(1, [3], [0.0], [1.0], "periodic")),
+    "2d_random67x45_mixed": lambda: (lambda p: (p, W.random_field(p, seed=6)))(
+        W.uniform_problem(2, [67, 45], [0.0, 0.0], [1.0, 1.0], ["periodic", "transmissive"])),
+    "2d_riemann3_96x80": lambda: W.riemann_2d(96, ny=80),
+    "2d_random5x7_reflective": lambda: (lambda p: (p, W.random_field(p, seed=7)))(
+        W.uniform_problem(2, [5, 7], [0.0, 0.0], [1.0, 1.0], "reflective")),
+    "3d_random21x18x13_mixed": lambda: (lambda p: (p, W.random_field(p, seed=8)))(
+        W.uniform_problem(3, [21, 18, 13], [0.0] * 3, [1.0] * 3,
+                          ["periodic", "transmissive", "reflective"])),
+    "3d_turbulence24": lambda: W.turbulence_3d(24),
+    "3d_random9x8x7_periodic": lambda: (lambda p: (p, W.random_field(p, seed=9)))(
+        W.uniform_problem(3, [9, 8, 7], [0.0] * 3, [1.0] * 3, "periodic")),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_parity(torch, B, orc, name):
+    prob, U = CASES[name]()
+    Rg, dg, ag, stg = _gpu_rhs(torch, B, prob, U)
+    ac, stc = orc.alpha(prob, U)
+    assert np.array_equal(ag, ac), (ag, ac)
+    assert stg == stc
+    Rc, dc = orc.rhs(prob, U, dump=True)
+    flips, rel, bitwise = compare(Rg, Rc, dg, dc, name)
+    assert flips == 0
+    assert rel <= REL
+    assert bitwise
+
+
+@pytest.mark.parametrize("name", ["1d_blast400_reflective", "2d_riemann3_96x80",
+                                  "3d_random21x18x13_mixed"])
+def test_rhs_parity_literal_decisions(torch, B, orc, name):
+    # every decision through the literal formula: same bits as the fast path
+    prob, U = CASES[name]()
+    Rf, df, _, _ = _gpu_rhs(torch, B, prob, U)
+    lit = prob.replace()
+    lit.literal_decisions = True
+    Rl, dl, _, _ = _gpu_rhs(torch, B, lit, U)
+    Rc, dc = orc.rhs(prob, U, dump=True)
+    flips, rel, bitwise = compare(Rl, Rc, dl, dc, name + " literal")
+    assert flips == 0 and bitwise
+    assert np.array_equal(Rf, Rl) and np.array_equal(df, dl)
+
+
+@pytest.mark.parametrize("scheme", ["fixed_ct", "linear5"])
+def test_rhs_parity_other_schemes(torch, B, orc, scheme):
+    prob = W.uniform_problem(2, [40, 33], [0.0, 0.0], [1.0, 1.0], "transmissive",
+                             scheme=scheme, ct_fixed=1e-6)
+    U = W.random_field(prob, seed=12)
+    Rg, dg, _, _ = _gpu_rhs(torch, B, prob, U)
+    Rc, dc = orc.rhs(prob, U, dump=True)
+    flips, rel, bitwise = compare(Rg, Rc, dg, dc, scheme)
+    assert flips == 0 and rel <= REL and bitwise
+
+
+def test_rhs_frozen_alpha(torch, B, orc):
+    prob, U = W.shu_osher(256)
+    alpha = np.array([7.5, 0.0, 0.0])
+    Rg, dg, ag, _ = _gpu_rhs(torch, B, prob, U, alpha=alpha)
+    assert np.array_equal(ag, alpha)
+    Rc, dc = orc.rhs(prob, U, alpha, dump=True)
+    flips, rel, bitwise = compare(Rg, Rc, dg, dc, "frozen alpha")
+    assert flips == 0 and bitwise
+
+
+def test_rhs_deterministic(torch, B):
+    prob, U = W.turbulence_3d(32)
+    R1, d1, _, _ = _gpu_rhs(torch, B, prob, U)
+    R2, d2, _, _ = _gpu_rhs(torch, B, prob, U)
+    assert np.array_equal(R1, R2) and np.array_equal(d1, d2)
+
+
+def test_free_stream_gpu(torch, B):
+    prob = W.uniform_problem(3, [17, 9, 11], [0.0] * 3, [1.0] * 3, "periodic")
+    U = W.conserved(np.full(prob.shape[1:], 1.1), [0.2, -0.1, 0.3], 0.9, 1.4)
+    Rg, _, _, _ = _gpu_rhs(torch, B, prob, U)
+    assert np.all(Rg == 0.0)
+
+
+# --------------------------------------------------------------------------
+# SSP-RK3 steps
+# --------------------------------------------------------------------------
+def _gpu_steps(torch, B, prob, U, cfl, t_end, nsteps):
+    S = B.Solver(prob)
+    S.init(0.0, t_end, cfl)
+    Ud = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    for _ in range(nsteps):
+        S.step(Ud)
+    torch.cuda.synchronize()
+    return Ud.cpu().numpy(), S.read_ctrl()
+
+
+@pytest.mark.parametrize("name,steps", [("1d_sod200", 12), ("2d_riemann3_96x80", 4),
+                                        ("3d_random21x18x13_mixed", 3), ("3d_turbulence24", 3)])
+def test_step_parity(torch, B, orc, name, steps):
+    prob, U = CASES[name]()
+    Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
+    Uc = U.copy()
+    t = 0.0
+    for _ in range(steps):
+        Uc, t, dt, a9, st = orc.step(prob, Uc, 0.5, t, 1e9)
+    assert c.nsteps == steps and c.status == 0
+    assert c.t == t and c.dt == dt
+    assert np.array_equal(np.array(c.alpha), a9)
+    print(f"[step parity] {name}: bitwise={np.array_equal(Ug, Uc)} "
+          f"max_abs={np.abs(Ug - Uc).max():.3e}", flush=True)
+    assert np.array_equal(Ug, Uc)
+
+
+def test_sod_run_to_t_end(torch, B, orc):
+    from oracle import riemann
+    prob, U = W.sod(200)
+    Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 0.2, 400)
+    assert c.t == 0.2
+    Uc, t, k = orc.run(prob, U, 0.5, t_end=0.2)
+    assert c.nsteps == k
+    assert np.array_equal(Ug, Uc)
+    r, _, _ = riemann.solution(W.SOD_LEFT, W.SOD_RIGHT, prob.centres(0), 0.2, x0=0.5)
+    assert np.mean(np.abs(Ug[0, 0, 0] - r)) < 1e-2
+
+
+def test_replay_step(torch, B, orc):
+    prob, U = W.adjoint_case(512)
+    S = B.Solver(prob)
+    S.init(0.0, 1e9, 0.5)
+    c = S.read_ctrl()
+    c.replay = 1
+    c.dt = 1.3e-4
+    a9 = np.array([[9.0, 0, 0], [9.5, 0, 0], [10.0, 0, 0]])
+    for s in range(3):
+        for k in range(3):
+            c.alpha[s][k] = a9[s, k]
+    S.write_ctrl(c)
+    Ud = torch.from_numpy(U.copy()).cuda()
+    S.step(Ud)
+    torch.cuda.synchronize()
+    Uc, t, dt, a9c, st = orc.step(prob, U, 0.5, 0.0, 1e9, replay=(1.3e-4, a9))
+    assert np.array_equal(Ud.cpu().numpy(), Uc)
+    c2 = S.read_ctrl()
+    assert c2.t == 1.3e-4 and c2.nsteps == 1
+
+
+def test_nonphysical_status_and_rollback(torch, B, orc):
+    prob, U = W.blast_waves(400)
+    S = B.Solver(prob)
+    S.init(0.0, 0.038, 0.5)
+    Ud = torch.from_numpy(U.copy()).cuda()
+    Uc = U.copy()
+    t = 0.0
+    for k in range(40):
+        before = Ud.clone()
+        S.step(Ud)
+        Uc2, t, dt, a9, st = orc.step(prob, Uc, 0.5, t, 0.038)
+        c = S.read_ctrl()
+        if st:
+            assert c.status == 3
+            assert torch.equal(Ud, before)  # the failed step left U unchanged
+            assert c.nsteps == k
+            S.step(Ud)  # sticky: later steps are no-ops
+            assert torch.equal(Ud, before)
+            return
+        assert c.status == 0
+        assert np.array_equal(Ud.cpu().numpy(), Uc2)
+        Uc = Uc2
+    pytest.fail("oracle never flagged the blast-wave state")
+
+
+# --------------------------------------------------------------------------
+# Full-size shapes: sampled cells against the oracle, computed one by one
+# --------------------------------------------------------------------------
+def _sampled(torch, B, orc, prob, U, nsample, seed):
+    rng = np.random.default_rng(seed)
+    cells = np.unique(rng.integers(0, prob.ncell, nsample))
+    S = B.Solver(prob)
+    Ud = torch.from_numpy(U).cuda()
+    out, dec = S.rhs(Ud, decisions=True)
+    torch.cuda.synchronize()
+    a = S.alpha.cpu().numpy()
+    ac, _ = orc.alpha(prob, U)
+    assert np.array_equal(a, ac)
+    nc = prob.nc
+    Rg = out.reshape(nc, -1)[:, torch.from_numpy(cells).cuda()].cpu().numpy().T
+    Rc, dcell = orc.rhs_cells(prob, U, a, cells, dump=True)
+    # decisions of the two faces of each sampled cell per axis
+    n = prob.n + [1] * (3 - prob.ndim)
+    nx, ny = n[0], n[1]
+    off = 0
+    dflat = dec
+    idx = []
+    for d in range(prob.ndim):
+        nd = n[d]
+        lines = prob.ncell // nd
+        x, y, z = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+        pos = (x, y, z)[d]
+        line = (z * ny + y, z * nx + x, y * nx + x)[d]
+        base = off + (line * (nd + 1) + pos) * 2 * nc
+        idx.append(np.stack([base, base + 2 * nc], axis=1))
+        off += lines * (nd + 1) * 2 * nc
+    idx = np.stack(idx, axis=1)  # [cell, axis, face]
+    gi = torch.from_numpy((idx[..., None] + np.arange(2 * nc)).reshape(-1)).cuda()
+    dg = dflat[gi].cpu().numpy().reshape(dcell.shape)
+    flips = int(np.count_nonzero(dg != dcell))
+    scale = np.abs(Rc).max(axis=0)
+    rel = float((np.abs(Rg - Rc).max(axis=0) / np.where(scale > 0, scale, 1)).max())
+    print(f"[sampled parity] {prob.n}: cells={len(cells)} flips={flips} max_rel={rel:.3e} "
+          f"bitwise={np.array_equal(Rg, Rc)}", flush=True)
+    tot = out.reshape(nc, -1).sum(dim=1).cpu().numpy()
+    return flips, rel, np.array_equal(Rg, Rc), tot, out
+
+
+def test_full_size_3d_256_sampled(torch, B, orc):
+    prob, U = W.turbulence_3d(256)
+    flips, rel, bitwise, tot, out = _sampled(torch, B, orc, prob, U, 1500, 100)
+    assert flips == 0 and rel <= REL and bitwise
+    # periodic: the RHS sums to zero up to round-off (telescoping eq 2.2)
+    mag = out.abs().reshape(5, -1).sum(dim=1).cpu().numpy()
+    assert np.all(np.abs(tot) <= 1e-12 * mag)
+
+
+def test_full_size_2d_2048_sampled(torch, B, orc):
+    prob, U = W.riemann_2d(2048)
+    flips, rel, bitwise, _, _ = _sampled(torch, B, orc, prob, U, 3000, 101)
+    assert flips == 0 and rel <= REL and bitwise
