@@ -152,13 +152,15 @@ int teno_sweep(const teno_grid* g, int32_t axis, const double* U_dev,
                void* stream);
 
 /* Self-test of the device arithmetic the path relies on, for n inputs:
- * q[i] = a[i] / b[i] and s[i] = sqrt(a[i]), both correctly rounded (IEEE-754
- * binary64, round to nearest even) whenever operands and results lie in
- * [2^-900, 2^900] in magnitude (zero allowed for the numerator), and r[i]
- * = the approximate reciprocal of b[i] used by the decision fast path.  All
+ * q[i] = a[i] / b[i] by the general routine and q2[i] = a[i] / b[i] by the
+ * reciprocal-based routine of the hot loops, s[i] = sqrt(a[i]) -- all
+ * correctly rounded (IEEE-754 binary64, round to nearest even) whenever
+ * operands and results lie in [2^-900, 2^900] in magnitude -- and r[i] = the
+ * approximate reciprocal of b[i] used by the decision fast path.  All
  * pointers are device pointers of n doubles. */
 int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
-                        double* s_dev, double* r_dev, int64_t n, void* stream);
+                        double* q2_dev, double* s_dev, double* r_dev, int64_t n,
+                        void* stream);
 
 /* One SSP-RK3 step of eq 4.1-4.3, in place on U_dev:
  *   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 u1 + 1/4 dt L(u1);

@@ -91,7 +91,7 @@ def lib():
         L.teno_rhs_debug.restype = ctypes.c_int
         L.teno_sweep.argtypes = [G, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.teno_sweep.restype = ctypes.c_int
-        L.teno_selftest_arith.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+        L.teno_selftest_arith.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
         L.teno_selftest_arith.restype = ctypes.c_int
         L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step.restype = ctypes.c_int
@@ -177,12 +177,13 @@ def teno_sweep(g, axis, U, Rout, alpha, Rin=None, stream=None):
 
 
 def selftest_arith(a, b, stream=None):
-    """(a / b, sqrt(a), approximate 1 / b) computed by the device."""
+    """(a / b, a / b via the reciprocal route, sqrt(a), approximate 1 / b)
+    computed by the device."""
     import torch
-    q, s, r = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
-    _check(lib().teno_selftest_arith(_ptr(a), _ptr(b), _ptr(q), _ptr(s), _ptr(r), a.numel(),
-                                     _stream(stream)), "teno_selftest_arith")
-    return q, s, r
+    q, q2, s, r = (torch.empty_like(a) for _ in range(4))
+    _check(lib().teno_selftest_arith(_ptr(a), _ptr(b), _ptr(q), _ptr(q2), _ptr(s), _ptr(r),
+                                     a.numel(), _stream(stream)), "teno_selftest_arith")
+    return q, q2, s, r
 
 
 def teno_step(g, U, ctrl, ws, stream=None):

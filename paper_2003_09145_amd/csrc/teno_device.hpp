@@ -98,6 +98,25 @@ __device__ __forceinline__ double rcp_nr(double b) {
     return __builtin_fma(r, e, r);
 }
 
+// Correctly rounded a / b from rb = rcp_nr(b): q0 = a rb, one Markstein step
+// q1 = q0 + (a - q0 b) rb (faithful), then the exact-remainder correction of
+// cr_div.  Outside the safe range it defers to cr_div.
+__device__ __forceinline__ double cr_div_r(double a, double b, double rb) {
+    const double q0 = a * rb;
+    const double e = __builtin_fma(-q0, b, a);
+    const double q = __builtin_fma(e, rb, q0);
+    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return cr_div(a, b);
+    const double r = __builtin_fma(-q, b, a);  // exact
+    if (r == 0.0) return q;
+    const bool up = (r > 0.0) == (b > 0.0);
+    const double qn = step_toward(q, up);
+    const double h = 0.5 * ((qn - q) * b);
+    const double ar = fabs(r), ah = fabs(h);
+    if (ar > ah) return qn;
+    if (ar == ah) return (__double_as_longlong(q) & 1ll) ? qn : q;
+    return q;
+}
+
 // TENO weights of eq 2.15 for each cutoff mask, omega_k = delta_k c_k / D with
 // D = (delta_0 c_0 + delta_1 c_1) + delta_2 c_2, folded at compile time in
 // IEEE round-to-nearest (the same operations and order as the runtime form).
@@ -124,10 +143,15 @@ __constant__ const double kOmega[8][3] = {
 // theta = 1 / (1 + x / H) (every operation rounded to nearest), m(x) >= B_l + j
 // holds exactly for x <= xthr[j - 1]; the host finds each threshold by
 // bisection over the doubles of the literal formula.
+constexpr int kMaxThr = 8;
 struct DecisionConsts {
-    double xthr[20];
-    int32_t nthr;       // B_u - B_l
-    int32_t literal;    // 1: evaluate every decision with the literal formula
+    double xthr[kMaxThr];  // unused entries hold -1 (never satisfied)
+    double ct_hi;          // largest C_T the scheme can use (10^-B_l or C_T)
+    double ct_lo;          // smallest C_T (10^-B_u or C_T)
+    int32_t nthr;          // B_u - B_l
+    int32_t literal;       // 1: evaluate every decision with the literal formula
+    int32_t need_m;        // 1: the ladder index is wanted (decision dumps)
+    int32_t pad_;
 };
 
 // Relative margin inside which an approximate decision value is not trusted
@@ -188,6 +212,7 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
 // combination with the eq 2.15 weights of the chosen mask.
 // *code receives m | (mask << 5).
 __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const DecisionConsts& K,
+                                                 const double* __restrict__ omega_lds,
                                                  double a, double b, double c, double d,
                                                  double e, uint32_t* code) {
     const double s01 = (a - 2.0 * b) + c;
@@ -205,9 +230,9 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
         cd = 7u << 5;
     } else {
         bool sure = K.literal == 0;
-        uint32_t m = 0;
-        uint32_t mask = 7u;
+        uint32_t m = 0, mask = 7u;
         if (sure) {
+            // Approximate gamma_k (eq 2.8) from approximate chi~_k = tau / (beta_k + eps).
             const double tau = fabs(beta2 - beta0);
             const double t0 = tau * rcp_nr(beta0 + S.eps);
             const double t1 = tau * rcp_nr(beta1 + S.eps);
@@ -223,29 +248,39 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             y2 = y * y;
             const double g2 = (y2 * y2) * y2;
             const double sum = (g0 + g1) + g2;
-            const double rs = rcp_nr(sum);
-            const double chi0 = g0 * rs, chi1 = g1 * rs, chi2 = g2 * rs;
-            double ct;
-            if (S.scheme == 0) {
+            // chi_k = g_k / sum against the extreme cutoffs: a flag that is the
+            // same for every rung of the ladder needs no ladder index.
+            const double hi = K.ct_hi * (1.0 + kDecisionMargin) * sum;
+            const double lo = K.ct_lo * (1.0 - kDecisionMargin) * sum;
+            const bool k0 = g0 >= hi, k1 = g1 >= hi, k2 = g2 >= hi;
+            const bool c0 = g0 < lo, c1 = g1 < lo, c2 = g2 < lo;
+            sure = isfinite(sum) && (k0 || c0) && (k1 || c1) && (k2 || c2);
+            mask = (k0 ? 1u : 0u) | (k1 ? 2u : 0u) | (k2 ? 4u : 0u);
+            if (S.scheme == 0 && (K.need_m || !sure)) {
+                // ladder index from the thresholds of the literal mapping
                 double x = t0;
                 if (t1 > x) x = t1;
                 if (t2 > x) x = t2;
-                sure = isfinite(x);
+                bool msure = isfinite(x);
                 uint32_t above = 0;
-                for (int j = 0; j < K.nthr; ++j) {
+#pragma unroll
+                for (int j = 0; j < kMaxThr; ++j) {
                     const double T = K.xthr[j];
                     above += (x <= T) ? 1u : 0u;
-                    sure = sure && (fabs(x - T) > kDecisionMargin * T);
+                    msure = msure && (fabs(x - T) > kDecisionMargin * fabs(T));
                 }
                 m = (uint32_t)S.Bl + above;
-                ct = kLadder[m];
-            } else {
-                ct = S.ct_fixed;
+                if (!sure) {
+                    const double ct = kLadder[m];
+                    const double rs = rcp_nr(sum);
+                    const double x0 = g0 * rs, x1 = g1 * rs, x2 = g2 * rs;
+                    const double band = kDecisionMargin * ct;
+                    sure = isfinite(sum) && fabs(x0 - ct) > band && fabs(x1 - ct) > band &&
+                           fabs(x2 - ct) > band;
+                    mask = (x0 < ct ? 0u : 1u) | (x1 < ct ? 0u : 2u) | (x2 < ct ? 0u : 4u);
+                }
+                sure = sure && msure;
             }
-            const double band = kDecisionMargin * ct;
-            sure = sure && isfinite(sum) && fabs(chi0 - ct) > band && fabs(chi1 - ct) > band &&
-                   fabs(chi2 - ct) > band;
-            mask = (chi0 < ct ? 0u : 1u) | (chi1 < ct ? 0u : 2u) | (chi2 < ct ? 0u : 4u);
         }
         cd = m | (mask << 5);
         if (!sure) cd = teno5_decide_literal(S, beta0, beta1, beta2);
@@ -255,7 +290,8 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
     const double f0 = (kC1_3 * a - kC7_6 * b) + kC11_6 * c;
     const double f1 = (-kC1_6 * b + kC5_6 * c) + kC1_3 * d;
     const double f2 = (kC1_3 * c + kC5_6 * d) - kC1_6 * e;
-    return (kOmega[mask][0] * f0 + kOmega[mask][1] * f1) + kOmega[mask][2] * f2;
+    const double* w = omega_lds + 3 * mask;
+    return (w[0] * f0 + w[1] * f1) + w[2] * f2;
 }
 
 // Ghost-cell source along a swept axis: periodic wrap, zero-gradient copy or

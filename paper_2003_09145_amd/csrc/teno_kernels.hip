@@ -61,7 +61,7 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
 }
 
 template <int ND, int DIR, int W>
-__global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
@@ -84,8 +84,14 @@ __global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
     }
     const int64_t colbase = col * A.col_step;
     const int cap = A.ext_cap;
-    double* ext = smem + (size_t)wave * (cap * NV + 64 * NC);
-    double* fhs = ext + (size_t)cap * NV;
+    double* omega = smem;  // 24 doubles: eq 2.15 weights per cutoff mask
+    const int per_wave = (cap * NV > 64 * NC) ? cap * NV : 64 * NC;
+    double* ext = smem + 24 + (size_t)wave * per_wave;
+    // The face fluxes reuse the wave's own stencil buffer: LDS operations of
+    // one wave complete in order, so every stencil read of the wave precedes
+    // the first face-flux write.
+    double* fhs = ext;
+    if (threadIdx.x < 24) omega[threadIdx.x] = kOmega[threadIdx.x / 3][threadIdx.x % 3];
 
     const int64_t F0 = k * kCellsPerChunk;
     const int64_t F = F0 + lane;
@@ -116,15 +122,16 @@ __global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
         // primitives (natural order), as u_k = m_k / rho, p = (gamma-1)(E - ke)
         const double rho = q[0];
         double u[ND];
+        const double rrho = rcp_nr(rho);
 #pragma unroll
-        for (int kk = 0; kk < ND; ++kk) u[kk] = cr_div(q[1 + kk], rho);
+        for (int kk = 0; kk < ND; ++kk) u[kk] = cr_div_r(q[1 + kk], rho, rrho);
         double mu = q[1] * u[0];
 #pragma unroll
         for (int kk = 1; kk < ND; ++kk) mu = mu + q[1 + kk] * u[kk];
         const double ke = 0.5 * mu;
         const double E = q[NC - 1];
         const double p = gm1 * (E - ke);
-        const double H = cr_div(E + p, rho);
+        const double H = cr_div_r(E + p, rho, rrho);
         // flux along DIR (natural order)
         double Fl[NC];
         Fl[0] = q[1 + DIR];
@@ -154,7 +161,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
         const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
         // Roe average of cells i (o+2) and i+1 (o+3)
         const double rl = sr[o + 2], rr = sr[o + 3];
-        const double wsum = cr_div(1.0, rl + rr);
+        const double rsum = rl + rr;
+        const double wsum = cr_div_r(1.0, rsum, rcp_nr(rsum));
         double ub[ND];
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk)
@@ -165,8 +173,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
         for (int kk = 1; kk < ND; ++kk) q2 = q2 + ub[kk] * ub[kk];
         const double c2 = gm1 * (Hb - 0.5 * q2);
         const double cs = cr_sqrt(c2);
-        const double ci = cr_div(1.0, cs);
-        const double b1 = cr_div(gm1, c2);
+        const double ci = cr_div_r(1.0, cs, rcp_nr(cs));
+        const double b1 = cr_div_r(gm1, c2, rcp_nr(c2));
         const double b2 = (0.5 * q2) * b1;
         const double un = ub[DIR];
         double ut[ND > 1 ? ND - 1 : 1];
@@ -174,102 +182,116 @@ __global__ __launch_bounds__(64 * W) void k_sweep(SweepArgs A) {
         for (int kk = 1; kk < ND; ++kk) ut[kk - 1] = ub[LO::tan_axis(kk)];
 
         double Fh[NC];  // local order accumulators of R * fhat
-        uint32_t codes[2 * NC];
 #pragma unroll
+        for (int qq = 0; qq < NC; ++qq) Fh[qq] = 0.0;
+        // oracle line numbering of the decision dump: x: k*ny + j; y: k*nx + i; z: j*nx + i
+        uint8_t* o8 = nullptr;
+        if (A.dump != nullptr) {
+            const int64_t gline = (DIR == 0) ? bl : bl * A.ncols + col;
+            o8 = A.dump + (gline * np1 + phi) * (2 * NC);
+        }
+        // products shared by the eigenvector entries (each rounded once, as in
+        // the dense oracle matrices)
+        const double unci = un * ci, b1un = b1 * un, unc = un * cs, hq2 = 0.5 * q2;
+        double b1ut[ND > 1 ? ND - 1 : 1];
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) b1ut[kk - 1] = b1 * ut[kk - 1];
+
+        // Characteristic fields one at a time (s is uniform across the wave, so
+        // the field-type branches are scalar): project the split fluxes of the
+        // stencil on the left eigenvector, reconstruct f^+ and f^-, and add
+        // R[:, s] * fhat_s to the face flux.
+#pragma unroll 1
         for (int s = 0; s < NC; ++s) {
-            // left eigenvector row s (local order)
+            const bool acoustic = (s == 0 || s == NC - 1);
+            const bool entropy = (s == 1);
+            const bool shear = !acoustic && !entropy;
             double Lr[NC];
-            if (s == 0 || s == NC - 1) {
-                const double sg = (s == 0) ? 1.0 : -1.0;
-                Lr[0] = (s == 0) ? 0.5 * (b2 + un * ci) : 0.5 * (b2 - un * ci);
-                Lr[1] = (s == 0) ? 0.5 * (-(b1 * un) - ci) : 0.5 * (-(b1 * un) + ci);
+            if (acoustic) {
+                const bool minus = (s == 0);
+                Lr[0] = minus ? 0.5 * (b2 + unci) : 0.5 * (b2 - unci);
+                Lr[1] = minus ? 0.5 * (-b1un - ci) : 0.5 * (-b1un + ci);
 #pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-(b1 * ut[kk - 1]));
+                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-b1ut[kk - 1]);
                 Lr[NC - 1] = 0.5 * b1;
-                (void)sg;
-            } else if (s == 1) {
+            } else if (entropy) {
                 Lr[0] = 1.0 - b2;
-                Lr[1] = b1 * un;
+                Lr[1] = b1un;
 #pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = b1 * ut[kk - 1];
+                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = b1ut[kk - 1];
                 Lr[NC - 1] = -b1;
             } else {
+                double uts = ut[0];
+#pragma unroll
+                for (int kk = 2; kk < ND; ++kk) uts = (s == 1 + kk) ? ut[kk - 1] : uts;
 #pragma unroll
                 for (int qq = 0; qq < NC; ++qq) Lr[qq] = 0.0;
-                Lr[0] = -ut[s - 2];
+                Lr[0] = -uts;
             }
-            // project the split fluxes of the six stencil cells
-            double vp[5], vm[5];
+            double fh = 0.0;
+#pragma unroll 1
+            for (int sg = 0; sg < 2; ++sg) {
+                // f^+ on cells i-2..i+2, f^- on the mirrored stencil i+3..i-1
+                __asm__ __volatile__("" ::: "memory");
+                const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
+                double v[5];
 #pragma unroll
-            for (int jj = 0; jj < 6; ++jj) {
-                const int idx = o + jj;
-                double ap = 0.0, am = 0.0;
-                if (s == 0 || s == 1 || s == NC - 1) {
-                    ap = Lr[0] * ext[idx];
-                    am = Lr[0] * ext[(size_t)NC * cap + idx];
+                for (int j = 0; j < 5; ++j) {
+                    const int cj = sg ? 5 - j : j;
+                    double acc;
+                    if (shear) {
+                        acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
+                    } else {
+                        acc = Lr[0] * fb[cj];
 #pragma unroll
-                    for (int qq = 1; qq < NC; ++qq) {
-                        ap = ap + Lr[qq] * ext[(size_t)qq * cap + idx];
-                        am = am + Lr[qq] * ext[(size_t)(NC + qq) * cap + idx];
+                        for (int qq = 1; qq < NC; ++qq) acc = acc + Lr[qq] * fb[(size_t)qq * cap + cj];
                     }
-                } else {  // shear row: -u_t f_rho + f_{m_t}
-                    ap = Lr[0] * ext[idx] + ext[(size_t)(s) * cap + idx];
-                    am = Lr[0] * ext[(size_t)NC * cap + idx] + ext[(size_t)(NC + s) * cap + idx];
+                    v[j] = acc;
                 }
-                if (jj < 5) vp[jj] = ap;
-                if (jj > 0) vm[jj - 1] = am;
+                uint32_t code;
+                const double r = teno5_rec_fast(A.sch, A.dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
+                if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
+                fh = sg ? fh + r : r;
             }
-            uint32_t cp, cm;
-            const double rp = teno5_rec_fast(A.sch, A.dk, vp[0], vp[1], vp[2], vp[3], vp[4], &cp);
-            const double rm = teno5_rec_fast(A.sch, A.dk, vm[4], vm[3], vm[2], vm[1], vm[0], &cm);
-            codes[2 * s] = cp;
-            codes[2 * s + 1] = cm;
-            const double fh = rp + rm;
             // accumulate R[:, s] * fh in local order
-            if (s == 0) {
-                Fh[0] = fh;
-                Fh[1] = (un - cs) * fh;
+            if (acoustic) {
+                const bool minus = (s == 0);
+                Fh[0] = Fh[0] + fh;
+                Fh[1] = Fh[1] + (minus ? (un - cs) : (un + cs)) * fh;
 #pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = ut[kk - 1] * fh;
-                Fh[NC - 1] = (Hb - un * cs) * fh;
-            } else if (s == 1) {
+                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
+                Fh[NC - 1] = Fh[NC - 1] + (minus ? (Hb - unc) : (Hb + unc)) * fh;
+            } else if (entropy) {
                 Fh[0] = Fh[0] + fh;
                 Fh[1] = Fh[1] + un * fh;
 #pragma unroll
                 for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-                Fh[NC - 1] = Fh[NC - 1] + (0.5 * q2) * fh;
-            } else if (s == NC - 1) {
-                Fh[0] = Fh[0] + fh;
-                Fh[1] = Fh[1] + (un + cs) * fh;
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-                Fh[NC - 1] = Fh[NC - 1] + (Hb + un * cs) * fh;
+                Fh[NC - 1] = Fh[NC - 1] + hq2 * fh;
             } else {
-                Fh[s] = Fh[s] + fh;  // local slot s is tangential s - 1
-                Fh[NC - 1] = Fh[NC - 1] + ut[s - 2] * fh;
+#pragma unroll
+                for (int kk = 1; kk < ND; ++kk) {
+                    if (s == 1 + kk) {
+                        Fh[1 + kk] = Fh[1 + kk] + fh;
+                        Fh[NC - 1] = Fh[NC - 1] + ut[kk - 1] * fh;
+                    }
+                }
             }
         }
 #pragma unroll
         for (int qq = 0; qq < NC; ++qq) fhs[LO::nat(qq) * 64 + lane] = Fh[qq];
-        if (A.dump != nullptr) {
-            // oracle line numbering: x: k*ny + j; y: k*nx + i; z: j*nx + i
-            const int64_t gline = (DIR == 0) ? bl : bl * A.ncols + col;
-            uint8_t* o8 = A.dump + (gline * np1 + phi) * (2 * NC);
-#pragma unroll
-            for (int kk = 0; kk < 2 * NC; ++kk) o8[kk] = (uint8_t)codes[kk];
-        }
     }
     __syncthreads();
 
     // ---- flux difference and epilogue ---------------------------------------
     if (valid && lane > 0 && phi > 0) {
+        const double rdx = rcp_nr(A.dx);
         const int64_t cell = colbase + bl * A.line_step + (phi - 1) * A.stride;
         double r[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double diff = fhs[c * 64 + lane] - fhs[c * 64 + lane - 1];
             const double prev = (A.Rin != nullptr) ? A.Rin[c * A.ncell + cell] : 0.0;
-            r[c] = prev - cr_div(diff, A.dx);
+            r[c] = prev - cr_div_r(diff, A.dx, rdx);
         }
         if (A.rk == 0) {
 #pragma unroll
@@ -312,14 +334,15 @@ __global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ U, int
         for (int c = 0; c < NC; ++c) q[c] = U[c * ncell + i];
         const double rho = q[0];
         double u[ND];
+        const double rrho = rcp_nr(rho);
 #pragma unroll
-        for (int k = 0; k < ND; ++k) u[k] = cr_div(q[1 + k], rho);
+        for (int k = 0; k < ND; ++k) u[k] = cr_div_r(q[1 + k], rho, rrho);
         double mu = q[1] * u[0];
 #pragma unroll
         for (int k = 1; k < ND; ++k) mu = mu + q[1 + k] * u[k];
         const double ke = 0.5 * mu;
         const double p = gm1 * (q[NC - 1] - ke);
-        const double cs = cr_sqrt(cr_div(gamma * p, rho));
+        const double cs = cr_sqrt(cr_div_r(gamma * p, rho, rrho));
         if (!(rho > 0.0) || !(p > 0.0) || !isfinite(cs)) bad = true;
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
@@ -419,11 +442,12 @@ __global__ void k_ctrl_init(teno_ctrl* ctrl, double t0, double t_end, double cfl
 
 // Arithmetic self-test: the device's correctly rounded division and square
 // root and the approximate reciprocal used by the decision fast path.
-__global__ void k_selftest_arith(const double* a, const double* b, double* q, double* s,
-                                 double* r, int64_t n) {
+__global__ void k_selftest_arith(const double* a, const double* b, double* q, double* q2,
+                                 double* s, double* r, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
         q[i] = cr_div(a[i], b[i]);
+        q2[i] = cr_div_r(a[i], b[i], rcp_nr(b[i]));
         s[i] = cr_sqrt(a[i]);
         r[i] = rcp_nr(b[i]);
     }
@@ -501,12 +525,28 @@ static int lad_m_host(double x, double H, int Bl, int Bu) {
 // m(x) is non-increasing in x >= 0 (every operation is monotone), so for each
 // j = 1 .. B_u - B_l the set {x : m(x) >= B_l + j} is [0, X_j]; X_j is found
 // by bisection over the bit patterns of the non-negative doubles.
-static DecisionConsts decision_consts(const teno_grid* g) {
+static const double kLadderHost[21] = {1e0,   1e-1,  1e-2,  1e-3,  1e-4,  1e-5,  1e-6,
+                                       1e-7,  1e-8,  1e-9,  1e-10, 1e-11, 1e-12, 1e-13,
+                                       1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
+
+static DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
     DecisionConsts K;
     memset(&K, 0, sizeof(K));
     K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
+    K.need_m = need_m ? 1 : 0;
+    for (int j = 0; j < kMaxThr; ++j) K.xthr[j] = -1.0;
+    if (g->scheme == TENO_SCHEME_FIXED_CT) {
+        K.ct_hi = K.ct_lo = g->ct_fixed;
+        return K;
+    }
     if (g->scheme != TENO_SCHEME_LAD) return K;
+    K.ct_hi = kLadderHost[g->Bl];
+    K.ct_lo = kLadderHost[g->Bu];
     K.nthr = g->Bu - g->Bl;
+    if (K.nthr > kMaxThr) {  // more rungs than the fast path holds: literal decisions
+        K.literal = 1;
+        return K;
+    }
     for (int j = 1; j <= K.nthr; ++j) {
         uint64_t lo = 0, hi = 0x7ff0000000000000ull;  // m(0) = B_u, m(inf) = B_l
         while (hi - lo > 1) {
@@ -527,12 +567,16 @@ template <int ND, int DIR>
 static hipError_t launch_sweep_t(SweepArgs A, hipStream_t st) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;
-    const size_t per_wave = (size_t)(A.ext_cap * NV + 64 * NC) * sizeof(double);
-    if (4 * per_wave <= (size_t)kMaxLdsPerBlock) {
+    const size_t per_wave =
+        (size_t)((A.ext_cap * NV > 64 * NC) ? A.ext_cap * NV : 64 * NC) * sizeof(double);
+    const size_t table = 24 * sizeof(double);
+    if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
         const int64_t blocks = (A.nchunks + 3) / 4;
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 4>), dim3((unsigned)blocks), dim3(256), 4 * per_wave, st, A);
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 4>), dim3((unsigned)blocks), dim3(256),
+                           table + 4 * per_wave, st, A);
     } else {
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 1>), dim3((unsigned)A.nchunks), dim3(64), per_wave, st, A);
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 1>), dim3((unsigned)A.nchunks), dim3(64),
+                           table + per_wave, st, A);
     }
     return hipGetLastError();
 }
@@ -545,7 +589,7 @@ static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStre
     A.dx = g->dx[dir];
     A.ncell = ncell_of(g);
     A.sch = scheme_of(g);
-    A.dk = decision_consts(g);
+    A.dk = decision_consts(g, A.dump != nullptr);
     A.ext_cap = ext_cap_for(n);
     int64_t lines_per_col;
     if (dir == 0) {
@@ -653,15 +697,15 @@ int teno_rhs_debug(const teno_grid* g, const double* U, double* dUdt, const doub
     return rhs_common(g, U, dUdt, alpha_in, alpha_out, status, decisions, ws, ws_bytes, stream);
 }
 
-int teno_selftest_arith(const double* a, const double* b, double* q, double* s, double* r,
-                        int64_t n, void* stream) {
-    if (n < 0 || (n > 0 && (a == nullptr || b == nullptr || q == nullptr || s == nullptr ||
-                            r == nullptr)))
+int teno_selftest_arith(const double* a, const double* b, double* q, double* q2, double* s,
+                        double* r, int64_t n, void* stream) {
+    if (n < 0 || (n > 0 && (a == nullptr || b == nullptr || q == nullptr || q2 == nullptr ||
+                            s == nullptr || r == nullptr)))
         return TENO_ERR_ARG;
     if (n == 0) return TENO_OK;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_selftest_arith, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, a, b, q, s, r, n);
+                       (hipStream_t)stream, a, b, q, q2, s, r, n);
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
 }
 

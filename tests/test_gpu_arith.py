@@ -46,17 +46,19 @@ def test_division_and_sqrt_correctly_rounded(torch):
     b = np.concatenate([b, rng.permutation(x2)])
     ad = torch.from_numpy(a).cuda()
     bd = torch.from_numpy(b).cuda()
-    q, s, r = B.selftest_arith(ad, bd)
+    q, q2, s, r = B.selftest_arith(ad, bd)
     torch.cuda.synchronize()
-    q, s, r = q.cpu().numpy(), s.cpu().numpy(), r.cpu().numpy()
+    q, q2, s, r = q.cpu().numpy(), q2.cpu().numpy(), s.cpu().numpy(), r.cpu().numpy()
     with np.errstate(all="ignore"):
         qe, se, re_ = a / b, np.sqrt(a), 1.0 / b
     bad_q = np.nonzero(q != qe)[0]
+    bad_q2 = np.nonzero(q2 != qe)[0]
     bad_s = np.nonzero(s != se)[0]
-    print(f"[arith] {len(a)} operands: div mismatches {len(bad_q)}, sqrt mismatches {len(bad_s)}")
-    for i in bad_q[:5]:
-        print("   div", repr(a[i]), repr(b[i]), repr(q[i]), repr(qe[i]))
-    assert len(bad_q) == 0 and len(bad_s) == 0
+    print(f"[arith] {len(a)} operands: div mismatches {len(bad_q)}, reciprocal-route div "
+          f"mismatches {len(bad_q2)}, sqrt mismatches {len(bad_s)}")
+    for i in list(bad_q[:5]) + list(bad_q2[:5]):
+        print("   div", repr(a[i]), repr(b[i]), repr(q[i]), repr(q2[i]), repr(qe[i]))
+    assert len(bad_q) == 0 and len(bad_q2) == 0 and len(bad_s) == 0
     ulps = np.abs(r - re_) / np.spacing(np.abs(re_))
     print(f"[arith] approximate reciprocal: max error {ulps.max():.2f} ulp")
     assert ulps.max() <= 4.0
