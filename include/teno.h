@@ -174,6 +174,62 @@ int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
 int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
               void* ws_dev, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: nbatch independent 1D problems of uneven length, each with
+ * its own LF speed, time step, time and status (the method of Sec. 2-4 per
+ * problem).  Fields are packed component-major over the concatenated tubes:
+ *     U[c * total + off_b + i],  off_b = sum of the lengths of tubes < b,
+ * c = rho, rho*u, E.  One RK stage of every tube is one persistent kernel
+ * launch; teno_batch_run replays a captured HIP graph of 10 steps.
+ * ------------------------------------------------------------------------ */
+typedef struct teno_batch_plan teno_batch_plan; /* opaque */
+
+/* Build a plan (host call; allocates the plan's device tables and two stage
+ * buffers of 3*total doubles).  g supplies gamma, the scheme parameters and
+ * bc[0] (applied at both ends of every tube); its ndim/n/dx are ignored.
+ * lengths[nbatch] >= 3 and dx[nbatch] > 0 are host arrays.  Every tube uses
+ * CFL number cfl and stops at t_end (INFINITY: never).  tune_cache (nullable)
+ * is a file of earlier autotuning results; a matching entry selects the
+ * launch configuration. */
+int teno_batch_plan_create(const teno_grid* g, int64_t nbatch, const int64_t* lengths,
+                           const double* dx, double cfl, double t_end,
+                           const char* tune_cache, teno_batch_plan** plan);
+int teno_batch_plan_destroy(teno_batch_plan* plan);
+
+/* Total number of cells (sum of the lengths), or -1 for a null plan. */
+int64_t teno_batch_total_cells(const teno_batch_plan* plan);
+
+/* Reset every tube to t = 0 and compute its LF speed from U_dev (enqueued). */
+int teno_batch_init(teno_batch_plan* plan, const double* U_dev, void* stream);
+
+/* One SSP-RK3 step (eq 4.1-4.3) of every tube, in place: 3 launches. */
+int teno_batch_step(teno_batch_plan* plan, double* U_dev, void* stream);
+
+/* nsteps steps; whole blocks of 10 steps are replays of a HIP graph captured
+ * on the first call for this U_dev (the remainder is launched directly). */
+int teno_batch_run(teno_batch_plan* plan, double* U_dev, int64_t nsteps, void* stream);
+
+/* Pick the launch configuration (waves per block x persistent blocks per CU)
+ * by timing `steps` steps of every candidate on a scratch copy of U_dev
+ * (synchronous; allocates the scratch copy).  The result is appended to
+ * tune_cache (nullable); an existing matching entry is used instead of
+ * timing.  *best_ms (nullable) receives the best time per step, or -1 when
+ * the cache was used.  The plan's per-tube state is unspecified afterwards:
+ * call teno_batch_init. */
+int teno_batch_autotune(teno_batch_plan* plan, const double* U_dev, int32_t steps,
+                        const char* tune_cache, double* best_ms);
+
+/* Current / explicit launch configuration (waves per block 1, 2 or 4;
+ * persistent blocks per CU, 0 = one block per group of chunks). */
+int teno_batch_get_config(const teno_batch_plan* plan, int32_t* waves,
+                          int32_t* blocks_per_cu);
+int teno_batch_set_config(teno_batch_plan* plan, int32_t waves, int32_t blocks_per_cu);
+
+/* Copy the per-tube time, last dt, sticky status and step count to host
+ * arrays of nbatch entries (each nullable); synchronises the device. */
+int teno_batch_read(const teno_batch_plan* plan, double* t, double* dt, int32_t* status,
+                    int64_t* nsteps);
+
 #ifdef __cplusplus
 }
 #endif

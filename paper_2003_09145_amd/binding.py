@@ -62,7 +62,10 @@ assert CTRL_BYTES == 128
 
 # Every symbol declared in include/teno.h (checked by the ABI tests).
 SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_rhs", "teno_rhs_debug", "teno_sweep",
-           "teno_selftest_arith", "teno_step"]
+           "teno_selftest_arith", "teno_step",
+           "teno_batch_plan_create", "teno_batch_plan_destroy", "teno_batch_total_cells",
+           "teno_batch_init", "teno_batch_step", "teno_batch_run", "teno_batch_autotune",
+           "teno_batch_get_config", "teno_batch_set_config", "teno_batch_read"]
 
 _lib = None
 
@@ -95,6 +98,30 @@ def lib():
         L.teno_selftest_arith.restype = ctypes.c_int
         L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step.restype = ctypes.c_int
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        P = ctypes.c_void_p
+        L.teno_batch_plan_create.argtypes = [G, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl), dbl,
+                                             dbl, ctypes.c_char_p, ctypes.POINTER(P)]
+        L.teno_batch_plan_create.restype = ctypes.c_int
+        L.teno_batch_plan_destroy.argtypes = [P]
+        L.teno_batch_plan_destroy.restype = ctypes.c_int
+        L.teno_batch_total_cells.argtypes = [P]
+        L.teno_batch_total_cells.restype = i64
+        L.teno_batch_init.argtypes = [P, vp, vp]
+        L.teno_batch_init.restype = ctypes.c_int
+        L.teno_batch_step.argtypes = [P, vp, vp]
+        L.teno_batch_step.restype = ctypes.c_int
+        L.teno_batch_run.argtypes = [P, vp, i64, vp]
+        L.teno_batch_run.restype = ctypes.c_int
+        L.teno_batch_autotune.argtypes = [P, vp, i32, ctypes.c_char_p, ctypes.POINTER(dbl)]
+        L.teno_batch_autotune.restype = ctypes.c_int
+        L.teno_batch_get_config.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.teno_batch_get_config.restype = ctypes.c_int
+        L.teno_batch_set_config.argtypes = [P, i32, i32]
+        L.teno_batch_set_config.restype = ctypes.c_int
+        L.teno_batch_read.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                      ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.teno_batch_read.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -236,3 +263,77 @@ class Solver:
         import torch
         buf = torch.frombuffer(bytearray(bytes(c)), dtype=torch.uint8)
         self.ctrl.copy_(buf.to(self.device))
+
+
+class BatchPlan:
+    """A batched ragged-1D plan (teno_batch_plan) over packed fields
+    U[c, off_b + i] (float64 CUDA tensor of shape (3, total))."""
+
+    def __init__(self, lengths, dx, prob=None, cfl=0.5, t_end=float("inf"), tune_cache=None):
+        import numpy as np
+        base = dict(ndim=1, n=[3], dx=[1.0], bc="transmissive")
+        if prob is not None:
+            base.update({k: v for k, v in (prob.items() if isinstance(prob, dict) else
+                                            vars(prob).items()) if k not in ("ndim", "n", "dx")})
+        self.g = grid(base)
+        self.lengths = np.ascontiguousarray(lengths, dtype=np.int64)
+        self.dx = np.ascontiguousarray(dx, dtype=np.float64)
+        self.nb = len(self.lengths)
+        self.tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        h = ctypes.c_void_p()
+        _check(lib().teno_batch_plan_create(
+            ctypes.byref(self.g), self.nb,
+            self.lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            self.dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(cfl), float(t_end),
+            self.tune_cache, ctypes.byref(h)), "teno_batch_plan_create")
+        self.h = h
+        self.total = int(lib().teno_batch_total_cells(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().teno_batch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, U, stream=None):
+        _check(lib().teno_batch_init(self.h, _ptr(U), _stream(stream)), "teno_batch_init")
+
+    def step(self, U, stream=None):
+        _check(lib().teno_batch_step(self.h, _ptr(U), _stream(stream)), "teno_batch_step")
+
+    def run(self, U, nsteps, stream=None):
+        _check(lib().teno_batch_run(self.h, _ptr(U), int(nsteps), _stream(stream)), "teno_batch_run")
+
+    def autotune(self, U, steps=3):
+        ms = ctypes.c_double()
+        _check(lib().teno_batch_autotune(self.h, _ptr(U), int(steps), self.tune_cache,
+                                         ctypes.byref(ms)), "teno_batch_autotune")
+        return ms.value
+
+    def config(self):
+        w, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().teno_batch_get_config(self.h, ctypes.byref(w), ctypes.byref(b)),
+               "teno_batch_get_config")
+        return w.value, b.value
+
+    def set_config(self, waves, blocks_per_cu):
+        _check(lib().teno_batch_set_config(self.h, int(waves), int(blocks_per_cu)),
+               "teno_batch_set_config")
+
+    def read(self):
+        import numpy as np
+        t = np.zeros(self.nb)
+        dt = np.zeros(self.nb)
+        st = np.zeros(self.nb, dtype=np.int32)
+        ns = np.zeros(self.nb, dtype=np.int64)
+        _check(lib().teno_batch_read(self.h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     dt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               "teno_batch_read")
+        return t, dt, st, ns

@@ -1,0 +1,101 @@
+// Host-side helpers shared by the HIP translation units of libteno.so:
+// argument validation and the per-launch scheme / decision constants.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/teno.h"
+#include "teno_device.hpp"
+
+namespace teno {
+
+inline int validate(const teno_grid* g) {
+    if (g == nullptr) return TENO_ERR_ARG;
+    if (g->ndim < 1 || g->ndim > 3) return TENO_ERR_ARG;
+    for (int k = 0; k < 3; ++k) {
+        if (k < g->ndim) {
+            if (g->n[k] < 3) return TENO_ERR_ARG;
+            if (!(g->dx[k] > 0.0)) return TENO_ERR_ARG;
+            if (g->bc[k] < 0 || g->bc[k] > 2) return TENO_ERR_ARG;
+        } else if (g->n[k] != 1) {
+            return TENO_ERR_ARG;
+        }
+    }
+    if (!(g->gamma > 1.0)) return TENO_ERR_ARG;
+    if (g->scheme < 0 || g->scheme > 2) return TENO_ERR_ARG;
+    if (g->scheme == 0) {
+        if (g->Bl < 0 || g->Bu > 20 || g->Bl > g->Bu || !(g->H > 0.0)) return TENO_ERR_ARG;
+    }
+    if (!(g->eps > 0.0)) return TENO_ERR_ARG;
+    if (g->flags & ~TENO_FLAG_LITERAL_DECISIONS) return TENO_ERR_ARG;
+    return TENO_OK;
+}
+
+inline SchemeParams scheme_of(const teno_grid* g) {
+    SchemeParams s;
+    s.gamma = g->gamma;
+    s.ct_fixed = g->ct_fixed;
+    s.H = g->H;
+    s.eps = g->eps;
+    s.scheme = g->scheme;
+    s.Bl = g->Bl;
+    s.Bu = g->Bu;
+    return s;
+}
+
+inline int ext_cap_for(int n) { return 69 + 5 * (63 / (n + 1) + 1); }
+
+// The literal LAD ladder index of eq 3.1-3.2 evaluated on the host (IEEE
+// binary64, round to nearest): m(x) = B_l + floor(theta (B_u - B_l)),
+// theta = 1 / (1 + x / H).
+inline int lad_m_host(double x, double H, int Bl, int Bu) {
+    const double theta = 1.0 / (1.0 + x / H);
+    if (theta >= 0.0) return Bl + (int)floor(theta * (double)(Bu - Bl));
+    return Bl;
+}
+
+// m(x) is non-increasing in x >= 0 (every operation is monotone), so for each
+// j = 1 .. B_u - B_l the set {x : m(x) >= B_l + j} is [0, X_j]; X_j is found
+// by bisection over the bit patterns of the non-negative doubles.
+inline const double kLadderHost[21] = {1e0,   1e-1,  1e-2,  1e-3,  1e-4,  1e-5,  1e-6,
+                                       1e-7,  1e-8,  1e-9,  1e-10, 1e-11, 1e-12, 1e-13,
+                                       1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
+
+inline DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
+    DecisionConsts K;
+    memset(&K, 0, sizeof(K));
+    K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
+    K.need_m = need_m ? 1 : 0;
+    for (int j = 0; j < kMaxThr; ++j) K.xthr[j] = -1.0;
+    if (g->scheme == TENO_SCHEME_FIXED_CT) {
+        K.ct_hi = K.ct_lo = g->ct_fixed;
+        return K;
+    }
+    if (g->scheme != TENO_SCHEME_LAD) return K;
+    K.ct_hi = kLadderHost[g->Bl];
+    K.ct_lo = kLadderHost[g->Bu];
+    K.nthr = g->Bu - g->Bl;
+    if (K.nthr > kMaxThr) {  // more rungs than the fast path holds: literal decisions
+        K.literal = 1;
+        return K;
+    }
+    for (int j = 1; j <= K.nthr; ++j) {
+        uint64_t lo = 0, hi = 0x7ff0000000000000ull;  // m(0) = B_u, m(inf) = B_l
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            double x;
+            memcpy(&x, &mid, sizeof(x));
+            if (lad_m_host(x, g->H, g->Bl, g->Bu) >= g->Bl + j)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        memcpy(&K.xthr[j - 1], &lo, sizeof(double));
+    }
+    return K;
+}
+
+
+}  // namespace teno

@@ -19,6 +19,8 @@
 
 #include "../../include/teno.h"
 #include "teno_device.hpp"
+#include "teno_face.hpp"
+#include "teno_host.hpp"
 
 namespace teno {
 
@@ -119,166 +121,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
         if (flip) q[1 + DIR] = -q[1 + DIR];
-        // primitives (natural order), as u_k = m_k / rho, p = (gamma-1)(E - ke)
-        const double rho = q[0];
-        double u[ND];
-        const double rrho = rcp_nr(rho);
-#pragma unroll
-        for (int kk = 0; kk < ND; ++kk) u[kk] = cr_div_r(q[1 + kk], rho, rrho);
-        double mu = q[1] * u[0];
-#pragma unroll
-        for (int kk = 1; kk < ND; ++kk) mu = mu + q[1 + kk] * u[kk];
-        const double ke = 0.5 * mu;
-        const double E = q[NC - 1];
-        const double p = gm1 * (E - ke);
-        const double H = cr_div_r(E + p, rho, rrho);
-        // flux along DIR (natural order)
-        double Fl[NC];
-        Fl[0] = q[1 + DIR];
-#pragma unroll
-        for (int kk = 0; kk < ND; ++kk)
-            Fl[1 + kk] = (kk == DIR) ? q[1 + kk] * u[DIR] + p : q[1 + kk] * u[DIR];
-        Fl[NC - 1] = (E + p) * u[DIR];
-        // global Lax-Friedrichs split in local order
-#pragma unroll
-        for (int qq = 0; qq < NC; ++qq) {
-            const int g = LO::nat(qq);
-            ext[(size_t)qq * cap + idx] = 0.5 * (Fl[g] + alpha * q[g]);
-            ext[(size_t)(NC + qq) * cap + idx] = 0.5 * (Fl[g] - alpha * q[g]);
-        }
-        ext[(size_t)(2 * NC) * cap + idx] = cr_sqrt(rho);
-#pragma unroll
-        for (int kk = 0; kk < ND; ++kk) ext[(size_t)(2 * NC + 1 + kk) * cap + idx] = u[kk];
-        ext[(size_t)(2 * NC + 1 + ND) * cap + idx] = H;
+        stage_cell<ND, DIR>(q, alpha, gm1, ext, cap, idx);
     }
     __syncthreads();
 
     // ---- numerical flux at this lane's face ----------------------------------
     if (valid) {
         const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of cell i-2
-        const double* sr = ext + (size_t)(2 * NC) * cap;
-        const double* uu = ext + (size_t)(2 * NC + 1) * cap;
-        const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
-        // Roe average of cells i (o+2) and i+1 (o+3)
-        const double rl = sr[o + 2], rr = sr[o + 3];
-        const double rsum = rl + rr;
-        const double wsum = cr_div_r(1.0, rsum, rcp_nr(rsum));
-        double ub[ND];
-#pragma unroll
-        for (int kk = 0; kk < ND; ++kk)
-            ub[kk] = (rl * uu[(size_t)kk * cap + o + 2] + rr * uu[(size_t)kk * cap + o + 3]) * wsum;
-        const double Hb = (rl * hh[o + 2] + rr * hh[o + 3]) * wsum;
-        double q2 = ub[0] * ub[0];
-#pragma unroll
-        for (int kk = 1; kk < ND; ++kk) q2 = q2 + ub[kk] * ub[kk];
-        const double c2 = gm1 * (Hb - 0.5 * q2);
-        const double cs = cr_sqrt(c2);
-        const double ci = cr_div_r(1.0, cs, rcp_nr(cs));
-        const double b1 = cr_div_r(gm1, c2, rcp_nr(c2));
-        const double b2 = (0.5 * q2) * b1;
-        const double un = ub[DIR];
-        double ut[ND > 1 ? ND - 1 : 1];
-#pragma unroll
-        for (int kk = 1; kk < ND; ++kk) ut[kk - 1] = ub[LO::tan_axis(kk)];
-
-        double Fh[NC];  // local order accumulators of R * fhat
-#pragma unroll
-        for (int qq = 0; qq < NC; ++qq) Fh[qq] = 0.0;
         // oracle line numbering of the decision dump: x: k*ny + j; y: k*nx + i; z: j*nx + i
         uint8_t* o8 = nullptr;
         if (A.dump != nullptr) {
             const int64_t gline = (DIR == 0) ? bl : bl * A.ncols + col;
             o8 = A.dump + (gline * np1 + phi) * (2 * NC);
         }
-        // products shared by the eigenvector entries (each rounded once, as in
-        // the dense oracle matrices)
-        const double unci = un * ci, b1un = b1 * un, unc = un * cs, hq2 = 0.5 * q2;
-        double b1ut[ND > 1 ? ND - 1 : 1];
+        double Fh[NC];
+        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh);
 #pragma unroll
-        for (int kk = 1; kk < ND; ++kk) b1ut[kk - 1] = b1 * ut[kk - 1];
-
-        // Characteristic fields one at a time (s is uniform across the wave, so
-        // the field-type branches are scalar): project the split fluxes of the
-        // stencil on the left eigenvector, reconstruct f^+ and f^-, and add
-        // R[:, s] * fhat_s to the face flux.
-#pragma unroll 1
-        for (int s = 0; s < NC; ++s) {
-            const bool acoustic = (s == 0 || s == NC - 1);
-            const bool entropy = (s == 1);
-            const bool shear = !acoustic && !entropy;
-            double Lr[NC];
-            if (acoustic) {
-                const bool minus = (s == 0);
-                Lr[0] = minus ? 0.5 * (b2 + unci) : 0.5 * (b2 - unci);
-                Lr[1] = minus ? 0.5 * (-b1un - ci) : 0.5 * (-b1un + ci);
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-b1ut[kk - 1]);
-                Lr[NC - 1] = 0.5 * b1;
-            } else if (entropy) {
-                Lr[0] = 1.0 - b2;
-                Lr[1] = b1un;
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = b1ut[kk - 1];
-                Lr[NC - 1] = -b1;
-            } else {
-                double uts = ut[0];
-#pragma unroll
-                for (int kk = 2; kk < ND; ++kk) uts = (s == 1 + kk) ? ut[kk - 1] : uts;
-#pragma unroll
-                for (int qq = 0; qq < NC; ++qq) Lr[qq] = 0.0;
-                Lr[0] = -uts;
-            }
-            double fh = 0.0;
-#pragma unroll 1
-            for (int sg = 0; sg < 2; ++sg) {
-                // f^+ on cells i-2..i+2, f^- on the mirrored stencil i+3..i-1
-                __asm__ __volatile__("" ::: "memory");
-                const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
-                double v[5];
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    const int cj = sg ? 5 - j : j;
-                    double acc;
-                    if (shear) {
-                        acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
-                    } else {
-                        acc = Lr[0] * fb[cj];
-#pragma unroll
-                        for (int qq = 1; qq < NC; ++qq) acc = acc + Lr[qq] * fb[(size_t)qq * cap + cj];
-                    }
-                    v[j] = acc;
-                }
-                uint32_t code;
-                const double r = teno5_rec_fast(A.sch, A.dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
-                if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
-                fh = sg ? fh + r : r;
-            }
-            // accumulate R[:, s] * fh in local order
-            if (acoustic) {
-                const bool minus = (s == 0);
-                Fh[0] = Fh[0] + fh;
-                Fh[1] = Fh[1] + (minus ? (un - cs) : (un + cs)) * fh;
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-                Fh[NC - 1] = Fh[NC - 1] + (minus ? (Hb - unc) : (Hb + unc)) * fh;
-            } else if (entropy) {
-                Fh[0] = Fh[0] + fh;
-                Fh[1] = Fh[1] + un * fh;
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-                Fh[NC - 1] = Fh[NC - 1] + hq2 * fh;
-            } else {
-#pragma unroll
-                for (int kk = 1; kk < ND; ++kk) {
-                    if (s == 1 + kk) {
-                        Fh[1 + kk] = Fh[1 + kk] + fh;
-                        Fh[NC - 1] = Fh[NC - 1] + ut[kk - 1] * fh;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int qq = 0; qq < NC; ++qq) fhs[LO::nat(qq) * 64 + lane] = Fh[qq];
+        for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
     }
     __syncthreads();
 
@@ -463,28 +322,6 @@ struct Scratch {  // small device area at the end of the workspace
     int32_t pad[7];
 };
 
-static int validate(const teno_grid* g) {
-    if (g == nullptr) return TENO_ERR_ARG;
-    if (g->ndim < 1 || g->ndim > 3) return TENO_ERR_ARG;
-    for (int k = 0; k < 3; ++k) {
-        if (k < g->ndim) {
-            if (g->n[k] < 3) return TENO_ERR_ARG;
-            if (!(g->dx[k] > 0.0)) return TENO_ERR_ARG;
-            if (g->bc[k] < 0 || g->bc[k] > 2) return TENO_ERR_ARG;
-        } else if (g->n[k] != 1) {
-            return TENO_ERR_ARG;
-        }
-    }
-    if (!(g->gamma > 1.0)) return TENO_ERR_ARG;
-    if (g->scheme < 0 || g->scheme > 2) return TENO_ERR_ARG;
-    if (g->scheme == 0) {
-        if (g->Bl < 0 || g->Bu > 20 || g->Bl > g->Bu || !(g->H > 0.0)) return TENO_ERR_ARG;
-    }
-    if (!(g->eps > 0.0)) return TENO_ERR_ARG;
-    if (g->flags & ~TENO_FLAG_LITERAL_DECISIONS) return TENO_ERR_ARG;
-    return TENO_OK;
-}
-
 static int64_t ncell_of(const teno_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
 
 static size_t state_bytes(const teno_grid* g) {
@@ -497,70 +334,6 @@ static size_t workspace_bytes_impl(const teno_grid* g) {
 
 static Scratch* scratch_of(const teno_grid* g, void* ws) {
     return (Scratch*)((char*)ws + 3 * state_bytes(g));
-}
-
-static SchemeParams scheme_of(const teno_grid* g) {
-    SchemeParams s;
-    s.gamma = g->gamma;
-    s.ct_fixed = g->ct_fixed;
-    s.H = g->H;
-    s.eps = g->eps;
-    s.scheme = g->scheme;
-    s.Bl = g->Bl;
-    s.Bu = g->Bu;
-    return s;
-}
-
-static int ext_cap_for(int n) { return 69 + 5 * (63 / (n + 1) + 1); }
-
-// The literal LAD ladder index of eq 3.1-3.2 evaluated on the host (IEEE
-// binary64, round to nearest): m(x) = B_l + floor(theta (B_u - B_l)),
-// theta = 1 / (1 + x / H).
-static int lad_m_host(double x, double H, int Bl, int Bu) {
-    const double theta = 1.0 / (1.0 + x / H);
-    if (theta >= 0.0) return Bl + (int)floor(theta * (double)(Bu - Bl));
-    return Bl;
-}
-
-// m(x) is non-increasing in x >= 0 (every operation is monotone), so for each
-// j = 1 .. B_u - B_l the set {x : m(x) >= B_l + j} is [0, X_j]; X_j is found
-// by bisection over the bit patterns of the non-negative doubles.
-static const double kLadderHost[21] = {1e0,   1e-1,  1e-2,  1e-3,  1e-4,  1e-5,  1e-6,
-                                       1e-7,  1e-8,  1e-9,  1e-10, 1e-11, 1e-12, 1e-13,
-                                       1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
-
-static DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
-    DecisionConsts K;
-    memset(&K, 0, sizeof(K));
-    K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
-    K.need_m = need_m ? 1 : 0;
-    for (int j = 0; j < kMaxThr; ++j) K.xthr[j] = -1.0;
-    if (g->scheme == TENO_SCHEME_FIXED_CT) {
-        K.ct_hi = K.ct_lo = g->ct_fixed;
-        return K;
-    }
-    if (g->scheme != TENO_SCHEME_LAD) return K;
-    K.ct_hi = kLadderHost[g->Bl];
-    K.ct_lo = kLadderHost[g->Bu];
-    K.nthr = g->Bu - g->Bl;
-    if (K.nthr > kMaxThr) {  // more rungs than the fast path holds: literal decisions
-        K.literal = 1;
-        return K;
-    }
-    for (int j = 1; j <= K.nthr; ++j) {
-        uint64_t lo = 0, hi = 0x7ff0000000000000ull;  // m(0) = B_u, m(inf) = B_l
-        while (hi - lo > 1) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            double x;
-            memcpy(&x, &mid, sizeof(x));
-            if (lad_m_host(x, g->H, g->Bl, g->Bu) >= g->Bl + j)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        memcpy(&K.xthr[j - 1], &lo, sizeof(double));
-    }
-    return K;
 }
 
 template <int ND, int DIR>
