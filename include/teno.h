@@ -100,7 +100,12 @@ typedef struct teno_ctrl {
     int32_t replay;      /* 0: dt and alpha from the state; 1: taken from here   */
     int64_t nsteps;      /* number of completed steps                            */
     int32_t active;      /* internal: 1 while the current step is running        */
-    int32_t pad_;
+    int32_t want_digest; /* 1: accumulate the cutoff-mask digest below            */
+    uint64_t digest;     /* sum over every face of every stage of a 64-bit hash of
+                            (nsteps, stage, axis, face, the 2*ncomp cutoff masks):
+                            equal digests mean (with overwhelming probability)
+                            identical masks at every face, stage and step         */
+    uint64_t reserved_[2];
 } teno_ctrl;
 
 /* Bytes of device workspace that teno_rhs / teno_step / teno_rhs_adjoint need
@@ -109,9 +114,19 @@ typedef struct teno_ctrl {
 size_t teno_workspace_bytes(const teno_grid* g);
 
 /* Fill a device control block: t = t0, t_end, cfl, replay = 0, status = OK,
- * nsteps = 0 (enqueued on `stream`). */
+ * nsteps = 0, want_digest = 0, digest = 0 (enqueued on `stream`). */
 int teno_ctrl_init(teno_ctrl* ctrl_dev, double t0, double t_end, double cfl,
                    void* stream);
+
+/* Prepare ctrl_dev to replay a recorded step: copy dt and alpha[3][3] from
+ * recorded_dev (a control block saved after a teno_step), set replay = 1,
+ * status = OK and t_end = +inf; t, nsteps and the digest fields of ctrl_dev
+ * are kept (enqueued). */
+int teno_ctrl_replay(teno_ctrl* ctrl_dev, const teno_ctrl* recorded_dev, void* stream);
+
+/* Switch the cutoff-mask digest of later teno_step calls on (enable = 1) or
+ * off, and reset it to 0 (enqueued). */
+int teno_ctrl_digest(teno_ctrl* ctrl_dev, int32_t enable, void* stream);
 
 /* dUdt_dev = L(U_dev): the semi-discrete RHS of eq 2.2 summed over the axes
  * in the order x, y, z (dUdt = 0 - dF_x/dx - dF_y/dy - dF_z/dz), with
@@ -173,6 +188,36 @@ int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
  * ctrl.status and leaves U_dev at its value before the step. */
 int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
               void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint.  With the cutoff flags delta_k of eq 2.14 (hence the
+ * weights of eq 2.15) and the LF speeds held fixed, L is a smooth function of
+ * U; these entry points apply the transpose of its Jacobian A(U) = dL/dU and
+ * of one SSP-RK3 step.  The flags are recomputed from U with the forward
+ * arithmetic, so they are exactly the forward pass's.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for teno_rhs_adjoint / teno_step_adjoint (six state-sized
+ * buffers and 6 * ncomp doubles per face of the largest sweep).  0 for an
+ * invalid grid. */
+size_t teno_adjoint_workspace_bytes(const teno_grid* g);
+
+/* gradU_dev = A(U)^T lambda_dev with the LF speeds alpha_dev (3 device
+ * doubles) frozen.  Deterministic (fixed summation order, no floating-point
+ * atomics).  gradU must not overlap U or lambda. */
+int teno_rhs_adjoint(const teno_grid* g, const double* U_dev, const double* alpha_dev,
+                     const double* lambda_dev, double* gradU_dev, void* ws_dev,
+                     size_t ws_bytes, void* stream);
+
+/* Transpose of one SSP-RK3 step (eq 4.1-4.3) taken from state Un_dev with the
+ * dt and per-stage speeds recorded in ctrl_dev (dt, alpha[3][3], as left by
+ * the forward teno_step): the stage states are rebuilt with those frozen
+ * values, then lambda_dev (cotangent of the step's output) is replaced in
+ * place by the cotangent of Un:
+ *   l2 = 2/3 l + 2/3 dt A(u2)^T l;   l1 = 1/4 l2 + 1/4 dt A(u1)^T l2;
+ *   l <- 1/3 l + 3/4 l2 + l1 + dt A(u^n)^T l1. */
+int teno_step_adjoint(const teno_grid* g, const double* Un_dev, const teno_ctrl* ctrl_dev,
+                      double* lambda_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: nbatch independent 1D problems of uneven length, each with

@@ -53,16 +53,20 @@ class TenoCtrl(ctypes.Structure):
         ("replay", ctypes.c_int32),
         ("nsteps", ctypes.c_int64),
         ("active", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("want_digest", ctypes.c_int32),
+        ("digest", ctypes.c_uint64),
+        ("reserved_", ctypes.c_uint64 * 2),
     ]
 
 
 CTRL_BYTES = ctypes.sizeof(TenoCtrl)
-assert CTRL_BYTES == 128
+assert CTRL_BYTES == 152
 
 # Every symbol declared in include/teno.h (checked by the ABI tests).
-SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_rhs", "teno_rhs_debug", "teno_sweep",
+SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_ctrl_replay", "teno_ctrl_digest",
+           "teno_rhs", "teno_rhs_debug", "teno_sweep",
            "teno_selftest_arith", "teno_step",
+           "teno_adjoint_workspace_bytes", "teno_rhs_adjoint", "teno_step_adjoint",
            "teno_batch_plan_create", "teno_batch_plan_destroy", "teno_batch_total_cells",
            "teno_batch_init", "teno_batch_step", "teno_batch_run", "teno_batch_autotune",
            "teno_batch_get_config", "teno_batch_set_config", "teno_batch_read"]
@@ -88,6 +92,10 @@ def lib():
         L.teno_workspace_bytes.restype = ctypes.c_size_t
         L.teno_ctrl_init.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
         L.teno_ctrl_init.restype = ctypes.c_int
+        L.teno_ctrl_replay.argtypes = [vp, vp, vp]
+        L.teno_ctrl_replay.restype = ctypes.c_int
+        L.teno_ctrl_digest.argtypes = [vp, ctypes.c_int32, vp]
+        L.teno_ctrl_digest.restype = ctypes.c_int
         L.teno_rhs.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_rhs.restype = ctypes.c_int
         L.teno_rhs_debug.argtypes = [G, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -98,6 +106,12 @@ def lib():
         L.teno_selftest_arith.restype = ctypes.c_int
         L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step.restype = ctypes.c_int
+        L.teno_adjoint_workspace_bytes.argtypes = [G]
+        L.teno_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        L.teno_rhs_adjoint.argtypes = [G, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.teno_rhs_adjoint.restype = ctypes.c_int
+        L.teno_step_adjoint.argtypes = [G, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.teno_step_adjoint.restype = ctypes.c_int
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         P = ctypes.c_void_p
         L.teno_batch_plan_create.argtypes = [G, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl), dbl,
@@ -184,6 +198,15 @@ def ctrl_init(ctrl, t0, t_end, cfl, stream=None):
            "teno_ctrl_init")
 
 
+def ctrl_replay(ctrl, recorded, stream=None):
+    _check(lib().teno_ctrl_replay(_ptr(ctrl), _ptr(recorded), _stream(stream)), "teno_ctrl_replay")
+
+
+def ctrl_digest(ctrl, enable=True, stream=None):
+    _check(lib().teno_ctrl_digest(_ptr(ctrl), 1 if enable else 0, _stream(stream)),
+           "teno_ctrl_digest")
+
+
 def teno_rhs(g, U, dUdt, ws, alpha_in=None, alpha_out=None, status=None, stream=None):
     _check(lib().teno_rhs(ctypes.byref(g), _ptr(U), _ptr(dUdt), _ptr(alpha_in), _ptr(alpha_out),
                           _ptr(status), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
@@ -216,6 +239,22 @@ def selftest_arith(a, b, stream=None):
 def teno_step(g, U, ctrl, ws, stream=None):
     _check(lib().teno_step(ctypes.byref(g), _ptr(U), _ptr(ctrl), _ptr(ws),
                            ws.numel() * ws.element_size(), _stream(stream)), "teno_step")
+
+
+def adjoint_workspace_bytes(g: TenoGrid) -> int:
+    return int(lib().teno_adjoint_workspace_bytes(ctypes.byref(g)))
+
+
+def teno_rhs_adjoint(g, U, alpha, lam, gradU, ws, stream=None):
+    _check(lib().teno_rhs_adjoint(ctypes.byref(g), _ptr(U), _ptr(alpha), _ptr(lam), _ptr(gradU),
+                                  _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "teno_rhs_adjoint")
+
+
+def teno_step_adjoint(g, Un, ctrl, lam, ws, stream=None):
+    _check(lib().teno_step_adjoint(ctypes.byref(g), _ptr(Un), _ptr(ctrl), _ptr(lam), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)),
+           "teno_step_adjoint")
 
 
 def decisions_bytes(g: TenoGrid) -> int:

@@ -59,13 +59,14 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
 // i-2 .. i+3 at o .. o + 5): Roe average, left/right eigenvectors, projection
 // of the split fluxes, TENO5-LAD reconstruction of f+ and f- per
 // characteristic field, back-projection.  Fnat receives the flux in natural
-// component order; o8 (nullable) receives the 2 NC decision codes.
+// component order; o8 (nullable) receives the 2 NC decision codes and masks
+// (nullable, initialised by the caller) the 2 NC cutoff masks, 3 bits each.
 template <int ND, int DIR>
 __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int cap, int o,
                                       double gm1, const SchemeParams& sch,
                                       const DecisionConsts& dk,
                                       const double* __restrict__ omega, uint8_t* o8,
-                                      double* Fnat) {
+                                      double* Fnat, uint32_t* masks = nullptr) {
     constexpr int NC = ND + 2;
     using LO = LocalOrder<ND, DIR>;
     const double* sr = ext + (size_t)(2 * NC) * cap;
@@ -157,6 +158,7 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
             uint32_t code;
             const double r = teno5_rec_fast(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
             if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
+            if (masks != nullptr) *masks |= (code >> 5) << (3 * (2 * s + sg));
             fh = sg ? fh + r : r;
         }
         // accumulate R[:, s] * fh in local order

@@ -36,7 +36,10 @@ struct SweepArgs {
     const double* Un;       // u^n (rk == 2, 3)
     double* Uout;           // RK stage output (rk > 0)
     const double* alpha;    // LF speeds, 3 doubles (indexed by axis)
-    const teno_ctrl* ctrl;  // nullable: gating and dt
+    const teno_ctrl* ctrl;  // nullable: the sweep runs only while ctrl->active and OK
+    const double* dtp;      // dt of the fused RK stage (rk > 0)
+    unsigned long long* digest;  // nullable: cutoff-mask digest accumulator
+    int32_t axis;
     uint8_t* dump;          // nullable: decision bytes of this axis
     int64_t ncell;
     int64_t line_step;      // cell-index step between consecutive lines of a column
@@ -48,6 +51,7 @@ struct SweepArgs {
     int32_t n;              // cells along the swept axis
     int32_t bc;
     int32_t rk;             // 0: write RHS; 1..3: fused RK stage
+    int32_t stage;          // RK stage of this sweep (digest key; with ctrl->nsteps)
     int32_t ext_cap;        // LDS ext cells per wave
     double dx;
     SchemeParams sch;
@@ -60,6 +64,14 @@ struct SweepArgs {
 __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
     const int64_t q = G / 8, r = G % 8, x = b % 8;
     return x * q + (x < r ? x : r) + b / 8;
+}
+
+// 64-bit mixer (the splitmix64 finaliser) for the cutoff-mask digest.
+__device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
 }
 
 template <int ND, int DIR, int W>
@@ -126,6 +138,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     __syncthreads();
 
     // ---- numerical flux at this lane's face ----------------------------------
+    unsigned long long sig = 0ull;
     if (valid) {
         const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of cell i-2
         // oracle line numbering of the decision dump: x: k*ny + j; y: k*nx + i; z: j*nx + i
@@ -135,9 +148,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
             o8 = A.dump + (gline * np1 + phi) * (2 * NC);
         }
         double Fh[NC];
-        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh);
+        uint32_t masks = 0;
+        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh, &masks);
 #pragma unroll
         for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
+        // the key names the step and stage as well as the face, so masks that
+        // move in time past a face change the digest
+        const uint64_t when = (A.ctrl != nullptr ? 3ull * (uint64_t)A.ctrl->nsteps : 0ull) +
+                              (uint64_t)A.stage;
+        sig = mask_hash(mask_hash(when) ^ ((uint64_t)A.axis << 60) ^
+                        ((uint64_t)(col * A.ftot + Fc) << 30) ^ masks);
+    }
+    if (A.digest != nullptr && (A.ctrl == nullptr || A.ctrl->want_digest)) {
+        // a face shared by two chunks (lane 63 here, lane 0 of the next) counts once
+        unsigned long long v = (valid && (lane < 63 || F == A.ftot - 1)) ? sig : 0ull;
+#pragma unroll
+        for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
+        if (lane == 0 && v != 0ull) atomicAdd(A.digest, v);
     }
     __syncthreads();
 
@@ -156,7 +183,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
             for (int c = 0; c < NC; ++c) A.Rout[c * A.ncell + cell] = r[c];
         } else {
-            const double h = A.ctrl->dt;
+            const double h = *A.dtp;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const size_t at = (size_t)c * A.ncell + cell;
@@ -296,7 +323,25 @@ __global__ void k_ctrl_init(teno_ctrl* ctrl, double t0, double t_end, double cfl
     ctrl->replay = 0;
     ctrl->nsteps = 0;
     ctrl->active = 0;
-    ctrl->pad_ = 0;
+    ctrl->want_digest = 0;
+    ctrl->digest = 0ull;
+    ctrl->reserved_[0] = ctrl->reserved_[1] = 0ull;
+}
+
+__global__ void k_ctrl_replay(teno_ctrl* dst, const teno_ctrl* rec) {
+    if (threadIdx.x != 0) return;
+    dst->dt = rec->dt;
+    for (int s = 0; s < 3; ++s)
+        for (int k = 0; k < 3; ++k) dst->alpha[s][k] = rec->alpha[s][k];
+    dst->replay = 1;
+    dst->status = 0;
+    dst->t_end = INFINITY;
+}
+
+__global__ void k_ctrl_digest(teno_ctrl* ctrl, int enable) {
+    if (threadIdx.x != 0) return;
+    ctrl->want_digest = enable;
+    ctrl->digest = 0ull;
 }
 
 // Arithmetic self-test: the device's correctly rounded division and square
@@ -441,6 +486,32 @@ static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const d
     return TENO_OK;
 }
 
+// One RK stage with frozen speeds and dt (no gating): the sweeps of every
+// axis, the last one fused with the stage update of eq 4.1 (rk = 1), 4.2
+// (rk = 2) or 4.3 (rk = 3).  Used by the adjoint to rebuild stage states.
+hipError_t stage_frozen(const teno_grid* g, const double* Uin, const double* Un, double* Uout,
+                        double* R, const double* alpha, const double* dtp, int rk,
+                        hipStream_t st) {
+    for (int d = 0; d < g->ndim; ++d) {
+        SweepArgs A;
+        memset(&A, 0, sizeof(A));
+        A.U = Uin;
+        A.Rin = (d == 0) ? nullptr : R;
+        A.Rout = R;
+        A.alpha = alpha;
+        A.dtp = dtp;
+        A.axis = d;
+        if (d == g->ndim - 1) {
+            A.rk = rk;
+            A.Un = Un;
+            A.Uout = Uout;
+        }
+        const hipError_t e = launch_sweep(g, d, A, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace teno
 
 using namespace teno;
@@ -455,6 +526,18 @@ size_t teno_workspace_bytes(const teno_grid* g) {
 int teno_ctrl_init(teno_ctrl* ctrl, double t0, double t_end, double cfl, void* stream) {
     if (ctrl == nullptr || !(cfl > 0.0)) return TENO_ERR_ARG;
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, (hipStream_t)stream, ctrl, t0, t_end, cfl);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+int teno_ctrl_replay(teno_ctrl* dst, const teno_ctrl* recorded, void* stream) {
+    if (dst == nullptr || recorded == nullptr) return TENO_ERR_ARG;
+    hipLaunchKernelGGL(k_ctrl_replay, dim3(1), dim3(64), 0, (hipStream_t)stream, dst, recorded);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+int teno_ctrl_digest(teno_ctrl* ctrl, int32_t enable, void* stream) {
+    if (ctrl == nullptr) return TENO_ERR_ARG;
+    hipLaunchKernelGGL(k_ctrl_digest, dim3(1), dim3(64), 0, (hipStream_t)stream, ctrl, enable ? 1 : 0);
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
 }
 
@@ -523,6 +606,10 @@ int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t w
             A.Rout = R;
             A.alpha = &ctrl->alpha[s][0];
             A.ctrl = ctrl;
+            A.dtp = &ctrl->dt;
+            A.axis = d;
+            A.stage = s;
+            A.digest = (unsigned long long*)&ctrl->digest;
             if (d == g->ndim - 1) {
                 A.rk = s + 1;
                 A.Un = U;

@@ -1,0 +1,208 @@
+"""Discrete adjoint (teno_rhs_adjoint, teno_step_adjoint, the checkpointed
+trajectory gradient) against the oracle's forward-mode dual numbers (the
+same frozen cutoff flags and speeds) and against finite differences."""
+import numpy as np
+import pytest
+
+from paper_2003_09145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2003_09145_amd import binding
+    binding.lib()
+    return binding
+
+
+def _adj_rows(torch, B, prob, U, alpha, lams):
+    g = B.grid(prob)
+    ws = torch.empty(B.adjoint_workspace_bytes(g), dtype=torch.uint8, device="cuda")
+    Ud = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    ad = torch.from_numpy(np.asarray(alpha, dtype=np.float64)).cuda()
+    out = []
+    for lam in lams:
+        ld = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
+        gd = torch.empty_like(Ud)
+        B.teno_rhs_adjoint(g, Ud, ad, ld, gd, ws)
+        out.append(gd)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+SMALL = {
+    "1d_periodic": lambda: (lambda p: (p, W.random_field(p, seed=21)))(
+        W.uniform_problem(1, [20], [0.0], [1.0], "periodic")),
+    "1d_transmissive": lambda: W.shu_osher(24),
+    "1d_reflective": lambda: (lambda p: (p, W.random_field(p, seed=22)))(
+        W.uniform_problem(1, [17], [0.0], [1.0], "reflective")),
+    "2d_mixed": lambda: (lambda p: (p, W.random_field(p, seed=23)))(
+        W.uniform_problem(2, [8, 7], [0.0, 0.0], [1.0, 1.0], ["reflective", "periodic"])),
+    "3d_mixed": lambda: (lambda p: (p, W.random_field(p, seed=24)))(
+        W.uniform_problem(3, [5, 5, 4], [0.0] * 3, [1.0] * 3,
+                          ["transmissive", "periodic", "reflective"])),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_rhs_adjoint_full_jacobian(torch, B, orc, name):
+    prob, U = SMALL[name]()
+    a, _ = orc.alpha(prob, U)
+    n = U.size
+    eye = np.eye(n)
+    Jo = np.stack([orc.rhs_jvp(prob, U, eye[j].reshape(U.shape), a)[1].ravel()
+                   for j in range(n)], axis=1)          # columns J e_j
+    Jg = np.stack([r.ravel() for r in _adj_rows(torch, B, prob, U, a,
+                                                 [eye[k].reshape(U.shape) for k in range(n)])])
+    err = np.abs(Jg - Jo).max() / np.abs(Jo).max()
+    print(f"[adjoint] {name}: full Jacobian {n}x{n}, max rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name,mk", [
+    ("1d_shu_osher512", lambda: W.shu_osher(512)),
+    ("2d_random40x33", lambda: (lambda p: (p, W.random_field(p, seed=31)))(
+        W.uniform_problem(2, [40, 33], [0.0, 0.0], [1.0, 1.0], ["transmissive", "reflective"]))),
+    ("3d_turbulence12", lambda: W.turbulence_3d(12)),
+])
+def test_rhs_adjoint_dot_product(torch, B, orc, name, mk):
+    prob, U = mk()
+    a, _ = orc.alpha(prob, U)
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        lam = rng.normal(size=U.shape)
+        v = rng.normal(size=U.shape) * np.abs(U)
+        _, jv = orc.rhs_jvp(prob, U, v, a)
+        (jtl,) = _adj_rows(torch, B, prob, U, a, [lam])
+        lhs = float(np.sum(lam * jv))
+        rhs = float(np.sum(jtl * v))
+        scale = float(np.sum(np.abs(lam * jv)))
+        rel = abs(lhs - rhs) / scale
+        print(f"[adjoint] {name}: <l, Jv> = {lhs:.12e}, <J^T l, v> = {rhs:.12e}, rel {rel:.1e}",
+              flush=True)
+        assert rel <= 1e-12
+
+
+def _recorder(B, prob):
+    from paper_2003_09145_amd.adjoint import Recorder
+    return Recorder(prob)
+
+
+def _log_host(B, log):
+    recs = [B.TenoCtrl.from_buffer_copy(bytes(log[k].cpu().numpy())) for k in range(log.shape[0])]
+    dts = np.array([r.dt for r in recs])
+    alphas = np.array([np.array(r.alpha) for r in recs])
+    return dts, alphas
+
+
+def test_step_adjoint_dot_product(torch, B, orc):
+    prob, U = W.shu_osher(300)
+    rec = _recorder(B, prob)
+    Ud = torch.from_numpy(U.copy()).cuda()
+    UK, log, ckpt = rec.forward(Ud, 1, 0.5)
+    dts, alphas = _log_host(B, log)
+    rng = np.random.default_rng(8)
+    lam = rng.normal(size=U.shape)
+    v = rng.normal(size=U.shape) * np.abs(U)
+    UT, VT = orc.run_jvp(prob, U, v, dts, alphas)
+    assert np.array_equal(UT, UK.cpu().numpy())
+    g = rec.backward(torch.from_numpy(lam).cuda(), log, ckpt).cpu().numpy()
+    lhs, rhs = float(np.sum(lam * VT)), float(np.sum(g * v))
+    rel = abs(lhs - rhs) / float(np.sum(np.abs(lam * VT)))
+    print(f"[adjoint] one RK3 step: rel {rel:.1e}", flush=True)
+    assert rel <= 1e-12
+
+
+def _loss_setup(N, noise=0.01):
+    prob, U0 = W.adjoint_case(N, noise=noise)
+    _, Ut = W.adjoint_case(N, noise=0.0)
+    return prob, U0, Ut
+
+
+def test_trajectory_gradient_and_checkpoint_invariance(torch, B, orc):
+    N, steps = 512, 60
+    prob, U0, Utarget = _loss_setup(N)
+    dx = prob.dx[0]
+    rec = _recorder(B, prob)
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    # target: final density of the noise-free run
+    tgt, _, _ = rec.forward(torch.from_numpy(Utarget.copy()).cuda(), steps, 0.5)
+    rho_star = tgt[0].clone()
+    grads = {}
+    for seg in (20, 1, 60):
+        UK, log, ckpt = rec.forward(Ud, steps, 0.5, seg=seg)
+        lamT = torch.zeros_like(UK)
+        lamT[0] = dx * (UK[0] - rho_star)
+        grads[seg] = rec.backward(lamT, log, ckpt, seg=seg)
+    torch.cuda.synchronize()
+    assert torch.equal(grads[20], grads[1]) and torch.equal(grads[20], grads[60])
+    g = grads[20].cpu().numpy()
+    dts, alphas = _log_host(B, log)
+    lam = lamT.cpu().numpy()
+    rng = np.random.default_rng(9)
+    for trial in range(3):
+        v = rng.normal(size=U0.shape) * np.abs(U0) * 1e-3
+        _, VT = orc.run_jvp(prob, U0, v, dts, alphas)
+        lhs, rhs = float(np.sum(lam * VT)), float(np.sum(g * v))
+        rel = abs(lhs - rhs) / max(abs(lhs), 1e-300)
+        print(f"[adjoint] {steps}-step gradient vs forward mode: rel {rel:.1e}", flush=True)
+        assert rel <= 1e-10
+
+
+def test_gradient_finite_differences_with_digest(torch, B):
+    # d J / d rho0 (u0, p0 fixed) against central differences h = 1e-6 with
+    # replayed dt and speeds, at cells whose cutoff masks do not change
+    N, steps, ncheck = 2048, 100, 16
+    prob, U0, Utarget = _loss_setup(N)
+    dx = prob.dx[0]
+    rec = _recorder(B, prob)
+    tgt, _, _ = rec.forward(torch.from_numpy(Utarget.copy()).cuda(), steps, 0.5)
+    rho_star = tgt[0].clone()
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    UK, log, ckpt = rec.forward(Ud, steps, 0.5, digest=True)
+    base_digest = rec.digest()
+    lamT = torch.zeros_like(UK)
+    lamT[0] = dx * (UK[0] - rho_star)
+    lam0 = rec.backward(lamT, log, ckpt).cpu().numpy()
+    u0 = U0[1] / U0[0]
+    grad_rho = lam0[0] + u0 * lam0[1] + 0.5 * u0 * u0 * lam0[2]
+
+    def J(Uin):
+        UT = rec.replay(torch.from_numpy(Uin).cuda(), log, digest=True)
+        return 0.5 * dx * float(((UT[0] - rho_star) ** 2).sum()), rec.digest()
+
+    Jb, db = J(U0)
+    assert db == base_digest
+    rng = np.random.default_rng(3)
+    x = prob.centres(0)
+    cells = rng.choice(np.nonzero(x >= -4.0)[0], 64, replace=False)
+    h = 1e-6
+    checked = skipped = 0
+    for i in cells:
+        if checked == ncheck:
+            break
+        dU = np.zeros_like(U0)
+        dU[0, 0, 0, i] = 1.0
+        dU[1, 0, 0, i] = u0[0, 0, i]
+        dU[2, 0, 0, i] = 0.5 * u0[0, 0, i] ** 2
+        Jp, dp = J(U0 + h * dU)
+        Jm, dm = J(U0 - h * dU)
+        if dp != base_digest or dm != base_digest:
+            skipped += 1
+            continue
+        fd = (Jp - Jm) / (2 * h)
+        ad = grad_rho[0, 0, i]
+        assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12, (i, fd, ad)
+        checked += 1
+    print(f"[adjoint] FD check: {checked} cells within 1e-6, {skipped} skipped (mask change)",
+          flush=True)
+    assert checked == ncheck
