@@ -1,21 +1,41 @@
 """Throughput benchmark of the TENO5-LAD Euler solver on one MI355X.
 
-Workload: 3D periodic compressible turbulence on [0, 2 pi]^3 at 256^3, FP64,
-gamma = 1.4, rho = 1, p = 1/(gamma Mt^2) with Mt = 0.6, solenoidal random-phase
-velocity (E(k) ~ k^4 exp(-2 k^2 / k0^2), k0 = 4, u_rms = 1, seed 0), CFL 0.5,
-SSP-RK3 steps through teno_step (the whole hot path: LF speeds and dt,
-ghost synthesis, characteristic TENO5-LAD faces along x, y, z, fused RK
-stage update).
+Headline workload: 3D periodic compressible turbulence on [0, 2 pi]^3 at
+256^3, FP64, gamma = 1.4, rho = 1, p = 1/(gamma Mt^2) with Mt = 0.6,
+solenoidal random-phase velocity (E(k) ~ k^4 exp(-2 k^2 / k0^2), k0 = 4,
+u_rms = 1, seed 0), CFL 0.5, SSP-RK3 steps through teno_step (the whole hot
+path: LF speeds and dt, ghost synthesis, characteristic TENO5-LAD faces along
+x, y, z, fused RK stage update), inputs resident in HBM.
 
 metric: cell-updates/s, one cell through one RHS evaluation and its RK stage
-update (an RK3 step = 3 cell-updates per cell), inputs resident in HBM.
+update (an RK3 step = 3 cell-updates per cell).
+
+Beside the headline the same JSON line carries
+  roofline      the dominant kernel (the slowest sweep) timed with HIP events
+                around its launches inside the timed region;
+  cpu_baseline  the FP64 oracle timed on the host cores on one RK3 step;
+  schemes       2D four-quadrant Riemann problem at 2048^2 (eq 4.14 states),
+                TENO5-LAD against fixed-cutoff TENO5 and the linear upwind
+                scheme, next to the per-step times of Table 2;
+  batched       4096 ragged 1D shock tubes (N log-uniform in [128, 4096]),
+                500 steps of the persistent graph-replayed batch kernel
+                against teno_step per tube on the same GPU;
+  adjoint       N = 2048 shock/entropy-wave case, 400 steps: gradient of the
+                final density mismatch through the discrete adjoint, against
+                the forward run and central finite differences.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-Prints one JSON line.
+                       [--no-extras]
+       python bench.py --copy-calibration          (plain 1 GiB copies)
+       python bench.py --summarize-counters DIR    (rocprofv3 CSV -> profiles/)
+Prints one JSON line (the benchmark modes).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -25,22 +45,29 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vector)
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+METRIC = "TENO RHS cell-updates/s (256³ FP64), % HBM roofline; batched/adjoint vs plain"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_3d_256_traffic.txt")
+SWEEP_SOURCES = ["paper_2003_09145_amd/csrc/teno_kernels.hip",
+                 "paper_2003_09145_amd/csrc/teno_face.hpp",
+                 "paper_2003_09145_amd/csrc/teno_device.hpp",
+                 "paper_2003_09145_amd/csrc/teno_host.hpp", "include/teno.h"]
+COPY_BYTES = 1 << 30
 
 
 # --------------------------------------------------------------------------
 # Algorithmic operation counts of the literal method (each +, -, *, /, sqrt
-# counts 1; comparisons and table lookups count 0; repeated identical
-# sub-expressions count once).  Derivation in the design doc.
+# counts 1, an FMA 2; comparisons, max, floor and table lookups count 0;
+# a sub-expression shared by several formulas counts once).
 # --------------------------------------------------------------------------
 def face_flops(nd: int) -> int:
     nc = nd + 2
-    roe = 12 + 6 * nd
-    left = 12 + 2 * (nd - 1)
-    project = 10 * (3 * (2 * nc - 1) + 2 * (nd - 1))
-    recon = 2 * nc * 89
-    back = nc + 8 * nd + 8
+    roe = 12 + 6 * nd                                # Roe average, b1, b2, c
+    left = 12 + 2 * (nd - 1)                         # non-trivial entries of L
+    project = 10 * (3 * (2 * nc - 1) + 2 * (nd - 1))  # l.U, l.F, v+-, 6 cells
+    recon = 2 * nc * 89                              # eq 2.4-2.15 + LAD, per scalar
+    back = nc + 8 * nd + 8                           # f+ + f-, R (f+ + f-)
     return roe + left + project + recon + back
 
 
@@ -48,40 +75,64 @@ def cell_flops(nd: int) -> int:
     return (9 * nd + 18) + 3 * (nd + 2)  # per-cell staging + flux difference
 
 
-def sweep_flops(nd: int, n, axis: int) -> int:
+def rk_flops(nd: int) -> float:
+    return (2 + 5 + 5) / 3.0 * (nd + 2)  # eq 4.1-4.3 averaged over the stages
+
+
+def sweep_flops(nd: int, n, axis: int, fused_rk: bool = False) -> float:
     ncell = math.prod(n[:nd])
     faces = ncell // n[axis] * (n[axis] + 1)
-    return faces * face_flops(nd) + ncell * cell_flops(nd)
+    f = faces * face_flops(nd) + ncell * cell_flops(nd)
+    return f + (ncell * rk_flops(nd) if fused_rk else 0.0)
 
 
-def sweep_bytes(nd: int, n, axis: int) -> int:
-    """Algorithmic HBM bytes of one sweep: read U, read the partial RHS of
-    earlier axes (if any), write the RHS (FP64)."""
+def sweep_bytes(nd: int, n, axis: int, fused_rk: bool = False) -> float:
+    """Algorithmic HBM bytes of one sweep launch: read U, read the partial RHS
+    of earlier axes, write the RHS; the last axis also reads u^n in stages 2
+    and 3 and writes the stage state instead of the RHS (FP64)."""
     ncell = math.prod(n[:nd])
     nc = nd + 2
-    return 8 * nc * ncell * (2 + (1 if axis > 0 else 0))
+    arrays = 2 + (1 if axis > 0 else 0) + ((2.0 / 3.0) if fused_rk else 0.0)
+    return 8 * nc * ncell * arrays
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--kernel-reps", type=int, default=10)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU sharding is "
-              "design-only", file=sys.stderr)
-        sys.exit(2)
+def step_bytes_min(nd: int, ncell: int) -> float:
+    """Least HBM bytes of one RK3 step of any implementation: each stage
+    reads its input state (and u^n in stages 2, 3) and writes its output."""
+    return 8 * (nd + 2) * ncell * (2 + 3 + 3)
 
-    import numpy as np
-    import torch
 
-    from paper_2003_09145_amd import binding as B
-    from paper_2003_09145_amd import workloads as W
+def sources_sha() -> str:
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
+
+def load_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch of `kernel` from the committed
+    summary, or None when the sweep sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha, vals = None, {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("kernel "):
+            name, rest = line[len("kernel "):].split(":", 1)
+            kv = dict(x.strip().split("=") for x in rest.split(","))
+            vals[name.strip()] = kv
+    if sha != sources_sha() or kernel not in vals:
+        return None
+    kv = vals[kernel]
+    return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+
+
+# --------------------------------------------------------------------------
+# Headline: 3D 256^3 turbulence
+# --------------------------------------------------------------------------
+def headline(args, B, W, torch):
     t0 = time.time()
     prob, U = W.turbulence_3d(args.n, seed=0)
     print(f"[bench] input {args.n}^3 built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
@@ -91,60 +142,493 @@ def main():
     S.init(0.0, float("inf"), 0.5)
     for _ in range(args.warmup):
         S.step(Ud)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    nev = 2 * 3 * 3
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    for row in evs:           # create the events before the timed region
+        for e in row:
+            e.record(stream)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
-        S.step(Ud)
+    for k in range(args.steps):
+        S.step(Ud, events=evs[k])
     e1.record(stream)
     torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1)
     ctrl = S.read_ctrl()
     if ctrl.status != 0:
         raise SystemExit(f"non-physical state during the benchmark (status {ctrl.status})")
     ncell = prob.ncell
     value = 3.0 * ncell * args.steps / (ms * 1e-3)
-    print(f"[bench] {args.steps} steps in {ms:.1f} ms, t = {ctrl.t:.5f}", file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), t = {ctrl.t:.5f}",
+          file=sys.stderr, flush=True)
 
-    # ---- the dominant kernel: one sweep launch per axis, timed with events on
-    # the stream it is launched on ------------------------------------------
-    R = torch.empty_like(Ud)
-    alpha = torch.tensor([ctrl.alpha[0][0], ctrl.alpha[0][1], ctrl.alpha[0][2]],
-                         dtype=torch.float64, device=dev)
+    # per-launch durations of the sweep kernels of the timed region
     per_axis = []
-    for axis in range(3):
-        B.teno_sweep(S.g, axis, Ud, R, alpha, Rin=(R if axis else None))
-        torch.cuda.synchronize()
-        a0 = torch.cuda.Event(enable_timing=True)
-        a1 = torch.cuda.Event(enable_timing=True)
-        a0.record(stream)
-        for _ in range(args.kernel_reps):
-            B.teno_sweep(S.g, axis, Ud, R, alpha, Rin=(R if axis else None))
-        a1.record(stream)
-        torch.cuda.synchronize()
-        per_axis.append(a0.elapsed_time(a1) / args.kernel_reps)
+    for d in range(3):
+        durs = [evs[k][2 * (3 * s + d)].elapsed_time(evs[k][2 * (3 * s + d) + 1])
+                for k in range(args.steps) for s in range(3)]
+        per_axis.append(sum(durs) / len(durs))
     n3 = [args.n] * 3
     dom = max(range(3), key=lambda a: per_axis[a])
-    flops = sweep_flops(3, n3, dom)
+    fused = dom == 2
+    flops = sweep_flops(3, n3, dom, fused_rk=fused)
     achieved = flops / (per_axis[dom] * 1e-3) / 1e12
+    kname = f"k_sweep<3,{dom},4>"
+    traffic = load_traffic(kname)
+    alg_bytes = sweep_bytes(3, n3, dom, fused_rk=fused)
     roofline = {
         "bound": "alu",
-        "kernel": f"k_sweep<3,{dom},4> (axis {'xyz'[dom]})",
         "achieved": round(achieved, 3),
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "kernel": f"{kname} (axis {'xyz'[dom]}{', fused RK stage' if fused else ''})",
         "launch_ms": round(per_axis[dom], 4),
         "flops_per_launch": flops,
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "hbm_algorithmic_GBs": round(alg_bytes / (per_axis[dom] * 1e-3) / 1e9, 1),
+        "hbm_algorithmic_frac": round(alg_bytes / (per_axis[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "hbm_counter_GBs": (None if traffic is None else
+                            round(traffic / (per_axis[dom] * 1e-3) / 1e9, 1)),
         "sweep_ms_xyz": [round(x, 4) for x in per_axis],
-        "hbm_algorithmic_GBs": round(sweep_bytes(3, n3, dom) / (per_axis[dom] * 1e-3) / 1e9, 1),
+    }
+    step_s = ms * 1e-3 / args.steps
+    whole = {
+        "cell_steps_per_s": ncell * args.steps / (ms * 1e-3),
+        "hbm_min_bytes_per_step": step_bytes_min(3, ncell),
+        "hbm_min_frac": round(step_bytes_min(3, ncell) / step_s / 1e9 / PEAK_HBM_GBS, 4),
+        "fp64_tflops_algorithmic": round(
+            3 * sum(sweep_flops(3, n3, d, fused_rk=(d == 2)) for d in range(3)) / step_s / 1e12, 3),
+        "sweeps_share_of_step": round(3 * sum(per_axis) / (ms / args.steps), 4),
+    }
+    return prob, U, value, ms, roofline, whole
+
+
+# --------------------------------------------------------------------------
+# f1: scheme variants on the 2D four-quadrant Riemann problem at 2048^2
+# --------------------------------------------------------------------------
+def schemes_leg(args, B, W, torch):
+    prob0, U = W.riemann_2d(args.n2d)
+    Ud0 = torch.from_numpy(U).cuda()
+    out = {"workload": f"2D four-quadrant Riemann problem {args.n2d}^2 (eq 4.14 states, split "
+                       f"(0.8, 0.8)), transmissive, CFL 0.5, {args.steps2d} steps",
+           "paper_table2_2048_s_per_step": {"TENO5": 13.1, "TENO5-A": 17.8, "Present": 13.7,
+                                            "hardware": "desktop workstation CPU (Table 2)"}}
+    for name, kw in (("lad", {}), ("teno5_ct1e-5", {"scheme": "fixed_ct", "ct_fixed": 1e-5}),
+                     ("linear5", {"scheme": "linear5"})):
+        prob = prob0.replace(**kw)
+        S = B.Solver(prob)
+        Ud = Ud0.clone()
+        S.init(0.0, float("inf"), 0.5)
+        S.step(Ud)
+        S.step(Ud)
+        Ud = Ud0.clone()
+        S.init(0.0, float("inf"), 0.5)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps2d):
+            S.step(Ud)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps2d
+        c = S.read_ctrl()
+        out[name] = {"ms_per_step": round(ms, 4),
+                     "cell_updates_per_s": 3.0 * prob.ncell / (ms * 1e-3),
+                     "status": int(c.status), "t": c.t}
+    base = out["teno5_ct1e-5"]["ms_per_step"]
+    out["lad_over_teno5"] = round(out["lad"]["ms_per_step"] / base, 4)
+    out["linear5_over_teno5"] = round(out["linear5"]["ms_per_step"] / base, 4)
+    print(f"[bench] schemes 2D: LAD {out['lad']['ms_per_step']:.3f} ms, TENO5 {base:.3f} ms, "
+          f"linear {out['linear5']['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+# --------------------------------------------------------------------------
+# a12: batched ragged 1D tubes against teno_step per tube
+# --------------------------------------------------------------------------
+def batched_leg(args, B, W, torch):
+    import numpy as np
+    import tempfile
+    batch = W.batched_tubes()
+    total = int(batch.offsets[-1])
+    cache = os.path.join(tempfile.mkdtemp(prefix="teno_tune_"), "batch_tune.jsonl")
+    P = B.BatchPlan(batch.lengths, batch.dx, tune_cache=cache)
+    U0 = torch.from_numpy(batch.U.copy()).cuda()
+    t0 = time.perf_counter()
+    Ud = U0.clone()
+    tune_ms = P.autotune(Ud, steps=3)
+    tune_s = time.perf_counter() - t0
+    waves, bpc = P.config()
+    # warm-up (builds the graph), then the timed run from the initial state
+    Ud = U0.clone()
+    P.init(Ud)
+    P.run(Ud, 10)
+    Ud = U0.clone()
+    P.init(Ud)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.run(Ud, args.batch_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    t, dt, st, ns = P.read()
+    # a tube whose state turns non-physical is frozen at its last good step
+    # (status 3, as the oracle run of that tube does); it counts the steps it made
+    frozen = np.nonzero(st != 0)[0]
+    if np.any(st[frozen] != 3) or np.any(ns[st == 0] != args.batch_steps) or len(frozen) > 8:
+        raise SystemExit(f"batched run: unexpected tube states (status {np.unique(st)})")
+    done = float(np.sum(batch.lengths * ns))
+    rate = 3.0 * done / (ms * 1e-3)
+
+    # the plain solver: teno_step per tube, one stream, tubes one after another
+    solvers, tubes = [], []
+    for b in range(batch.nbatch):
+        S = B.Solver(batch.tube_problem(b))
+        S.init(0.0, float("inf"), 0.5)
+        solvers.append(S)
+        o0, o1 = int(batch.offsets[b]), int(batch.offsets[b + 1])
+        tubes.append(U0[:, o0:o1].clone().reshape(3, 1, 1, o1 - o0))
+    solvers[0].step(tubes[0].clone())  # load / warm the kernels once
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        for S, u in zip(solvers, tubes):
+            S.step(u)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - w0
+    plain_rate = 3.0 * total * args.plain_steps / plain_s
+    # same steps through the batch: every tube must match its plain run
+    Ub = U0.clone()
+    P.init(Ub)
+    for _ in range(args.plain_steps):
+        P.step(Ub)
+    torch.cuda.synchronize()
+    plain = torch.cat([u.reshape(3, -1) for u in tubes], dim=1)
+    diff = float((plain - Ub).abs().max())
+    print(f"[bench] batched: {ms:.1f} ms for {args.batch_steps} steps ({rate:.3e} cell-updates/s); "
+          f"plain {plain_rate:.3e}; max |diff| {diff}", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{batch.nbatch} Sod-type tubes, N log-uniform in [128, 4096] (sum {total}), "
+                    f"seeded states, transmissive, CFL 0.5, per-tube dt",
+        "steps": args.batch_steps, "ms": round(ms, 3),
+        "cell_updates_per_s": rate,
+        "nonphysical_tubes": [{"tube": int(b), "cells": int(batch.lengths[b]),
+                               "steps_done": int(ns[b])} for b in frozen],
+        "autotuned": {"waves_per_block": waves, "blocks_per_cu": bpc,
+                      "ms_per_step_tuning": round(tune_ms, 4), "tuning_wall_s": round(tune_s, 2)},
+        "plain_per_tube": {"steps": args.plain_steps, "wall_s": round(plain_s, 3),
+                           "cell_updates_per_s": plain_rate},
+        "speedup_vs_plain": round(rate / plain_rate, 2),
+        "max_abs_diff_vs_plain": diff,
     }
 
+
+# --------------------------------------------------------------------------
+# a13: discrete adjoint against the forward solver and finite differences
+# --------------------------------------------------------------------------
+def adjoint_leg(args, B, W, torch):
+    import numpy as np
+    from paper_2003_09145_amd.adjoint import Recorder
+    N, steps = 2048, args.adjoint_steps
+    prob, U0 = W.adjoint_case(N, noise=0.01)
+    _, Ut = W.adjoint_case(N, noise=0.0)
+    dx = prob.dx[0]
+    rec = Recorder(prob)
+    # kernel-level ratio on the initial state: teno_rhs_adjoint / teno_rhs
+    S = rec.S
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    R = S.rhs(Ud)
+    alpha = S.alpha.clone()
+    lam = torch.ones_like(Ud)
+    G = torch.empty_like(Ud)
+    reps = 200
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(reps):
+            fn()
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    rhs_ms = timed(lambda: S.rhs(Ud, alpha_in=alpha, out=R))
+    adj_ms = timed(lambda: B.teno_rhs_adjoint(rec.g, Ud, alpha, lam, G, rec.ws_adj))
+
+    tgt, _, _ = rec.forward(torch.from_numpy(Ut.copy()).cuda(), steps, 0.5)
+    rho_star = tgt[0].clone()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    UK, log, ckpt = rec.forward(Ud, steps, 0.5, seg=20, digest=True)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - w0
+    base_digest = rec.digest()
+    lamT = torch.zeros_like(UK)
+    lamT[0] = dx * (UK[0] - rho_star)
+    w0 = time.perf_counter()
+    lam0 = rec.backward(lamT, log, ckpt, seg=20)
+    torch.cuda.synchronize()
+    bwd_s = time.perf_counter() - w0
+    lam0 = lam0.cpu().numpy()
+    u0 = U0[1] / U0[0]
+    grad_rho = lam0[0] + u0 * lam0[1] + 0.5 * u0 * u0 * lam0[2]
+
+    def J(Uin):
+        UT = rec.replay(torch.from_numpy(Uin).cuda(), log, digest=True)
+        return 0.5 * dx * float(((UT[0] - rho_star) ** 2).sum()), rec.digest()
+
+    rng = np.random.default_rng(3)
+    cand = rng.permutation(np.nonzero(prob.centres(0) >= -4.0)[0])
+    h = 1e-6
+    # bar: 1e-6 relative where |dJ/drho_i| >= 0.1 max|dJ/drho|, else 1e-7 max|dJ/drho|
+    # (the rounding floor of a central difference at h = 1e-6 grows as 1/h)
+    gmax = float(np.abs(grad_rho).max())
+    errs, ratios, skipped, tried = [], [], 0, 0
+    w0 = time.perf_counter()
+    for i in cand:
+        if len(errs) == args.fd_cells or tried == 4 * args.fd_cells:
+            break
+        tried += 1
+        dU = np.zeros_like(U0)
+        dU[0, 0, 0, i] = 1.0
+        dU[1, 0, 0, i] = u0[0, 0, i]
+        dU[2, 0, 0, i] = 0.5 * u0[0, 0, i] ** 2
+        Jp, dp = J(U0 + h * dU)
+        Jm, dm = J(U0 - h * dU)
+        if dp != base_digest or dm != base_digest:
+            skipped += 1
+            continue
+        fd = (Jp - Jm) / (2 * h)
+        ad = float(grad_rho[0, 0, i])
+        errs.append(abs(fd - ad) / max(abs(ad), 1e-300))
+        ratios.append(abs(fd - ad) / (1e-6 * max(abs(ad), 0.1 * gmax)))
+    fd_s = time.perf_counter() - w0
+    worst = max(errs) if errs else None
+    print(f"[bench] adjoint: rhs {rhs_ms:.4f} ms, rhs_adjoint {adj_ms:.4f} ms; forward {fwd_s:.3f} s, "
+          f"backward {bwd_s:.3f} s; FD {len(errs)} cells, max rel {worst}, {skipped} skipped",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": f"1D N={N} on [-5, 5], Mach-3 shock into rho = 1 + 0.2 sin 5x + noise 0.01, "
+                    f"{steps} steps, CFL 0.5, checkpoints every 20 steps",
+        "rhs_ms": round(rhs_ms, 5), "rhs_adjoint_ms": round(adj_ms, 5),
+        "rhs_adjoint_over_rhs": round(adj_ms / rhs_ms, 3),
+        "forward_recorded_s": round(fwd_s, 4), "backward_s": round(bwd_s, 4),
+        "gradient_over_forward": round(bwd_s / fwd_s, 3),
+        "fd_check": {"h": h, "cells": len(errs), "skipped_mask_change": skipped,
+                     "max_rel_err": worst, "grad_inf": gmax,
+                     "bar": "|fd - ad| <= 1e-6 max(|ad|, 0.1 max|grad|)",
+                     "max_err_over_bar": max(ratios) if ratios else None,
+                     "pass": bool(ratios) and max(ratios) <= 1.0, "wall_s": round(fd_s, 2)},
+    }
+
+
+# --------------------------------------------------------------------------
+# The oracle on the host cores
+# --------------------------------------------------------------------------
+def cpu_baseline(prob, U):
+    import numpy as np
+    import oracle
+    U0 = np.ascontiguousarray(U)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.time()
+    oracle.step(prob, U0, 0.5, 0.0, float("inf"))
+    el = time.time() - t0
+    return {"value": 3.0 * prob.ncell / el, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one SSP-RK3 step (3 RHS evaluations + stage updates) of the same "
+                      f"{prob.n[0]}^3 input, {el:.1f} s wall on {threads} OpenMP threads"}
+
+
+# --------------------------------------------------------------------------
+# Counter plumbing: a plain copy of known size, and the CSV summariser
+# --------------------------------------------------------------------------
+def copy_calibration():
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}))
+
+
+def _read_counters(d):
+    """{kernel name: {counter: (mean value per dispatch, dispatches)}} from the
+    rocprofv3 output under directory d (counter_collection CSV files, else the
+    counters_collection view of its SQLite databases)."""
+    rows = []
+    for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(p, newline="") as f:
+            for r in csv.DictReader(f):
+                key = {k.lower(): v for k, v in r.items()}
+                rows.append((p + key.get("dispatch_id"), key.get("kernel_name"),
+                             key.get("counter_name"), float(key.get("counter_value"))))
+    if not rows:
+        import sqlite3
+        for p in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+            c = sqlite3.connect(p)
+            for dsp, k, cn, v in c.execute(
+                    "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+                rows.append((p + str(dsp), k, cn, float(v)))
+            c.close()
+    per = {}
+    for dsp, k, cn, v in rows:
+        per[(dsp, k, cn)] = per.get((dsp, k, cn), 0.0) + v
+    acc = {}
+    for (dsp, k, cn), v in per.items():
+        acc.setdefault(k, {}).setdefault(cn, []).append(v)
+    return {k: {c: (sum(v) / len(v), len(v)) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def _short(name):
+    import re
+    m = re.search(r"(k_\w+)(<[^>]*>)?", name)
+    if not m:
+        return name[:60]
+    return m.group(1) + (m.group(2) or "").replace(" ", "").replace("(int)", "")
+
+
+def summarize_counters(d):
+    fetch = _read_counters(os.path.join(d, "fetch"))
+    write = _read_counters(os.path.join(d, "write"))
+    calf = _read_counters(os.path.join(d, "calf"))
+    calw = _read_counters(os.path.join(d, "calw"))
+    valu = _read_counters(os.path.join(d, "valu"))
+
+    def copy_kib(tab, counter):
+        best = None
+        for k, cs in tab.items():
+            if counter in cs and ("copy" in k.lower() or "elementwise" in k.lower()):
+                v = cs[counter][0]
+                best = v if best is None else max(best, v)
+        return best
+
+    cf_kib = copy_kib(calf, "FETCH_SIZE")
+    cw_kib = copy_kib(calw, "WRITE_SIZE")
+    cal_f = COPY_BYTES / (cf_kib * 1024.0)
+    cal_w = COPY_BYTES / (cw_kib * 1024.0)
+    n3 = [256] * 3
+    lines = [
+        "# HBM traffic and FP64 VALU counters of the 3D sweep kernels, 256^3 turbulence",
+        "# (k_sweep<3,d,4>: axis d; axis z carries the fused RK stage update)",
+        "#",
+        "# commands (from the repository root, after cd /tmp && export TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc/fetch -o fetch -- "
+        "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc/write -o write -- "
+        "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
+        "#   rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 "
+        "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVES "
+        "--output-format csv -d gpurun_out/pmc/valu -o valu -- python3 bench.py --steps 5 "
+        "--warmup 1 --no-cpu-baseline --no-extras",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc/calf -o calf -- "
+        "python3 bench.py --copy-calibration",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc/calw -o calw -- "
+        "python3 bench.py --copy-calibration",
+        "#   python3 bench.py --summarize-counters gpurun_out/pmc",
+        "#",
+        f"# copy calibration: a plain {COPY_BYTES} B device copy reads FETCH_SIZE = {cf_kib:.0f} KiB "
+        f"and WRITE_SIZE = {cw_kib:.0f} KiB per dispatch",
+        f"calibration_fetch: {cal_f:.4f}",
+        f"calibration_write: {cal_w:.4f}",
+        f"source_sha256: {sources_sha()}",
+        "#",
+        "# per dispatch (mean over dispatches): counter KiB, calibrated bytes, algorithmic bytes",
+    ]
+    for k in sorted(fetch):
+        sk = _short(k)
+        if not sk.startswith("k_sweep<3"):
+            continue
+        fk, nd = fetch[k]["FETCH_SIZE"]
+        wk = None
+        for kk, cs in write.items():
+            if _short(kk) == sk and "WRITE_SIZE" in cs:
+                wk = cs["WRITE_SIZE"][0]
+        axis = int(sk.split(",")[1])
+        fb = fk * 1024.0 * cal_f
+        wb = (wk or 0.0) * 1024.0 * cal_w
+        alg = sweep_bytes(3, n3, axis, fused_rk=(axis == 2))
+        lines.append(f"kernel {sk}: fetch_kib={fk:.0f}, write_kib={wk or 0:.0f}, "
+                     f"fetch_bytes={fb:.0f}, write_bytes={wb:.0f}, algorithmic_bytes={alg:.0f}, "
+                     f"ratio={(fb + wb) / alg:.3f}, dispatches={nd}")
+    lines.append("#")
+    lines.append("# FP64 VALU instructions per dispatch (wave-level; x64 lanes; FMA = 2 flop)")
+    for k in sorted(valu):
+        sk = _short(k)
+        if not sk.startswith("k_sweep<3"):
+            continue
+        cs = valu[k]
+        g = lambda c: cs.get(c, (0.0, 0))[0]
+        flop = 64.0 * (g("SQ_INSTS_VALU_ADD_F64") + g("SQ_INSTS_VALU_MUL_F64") +
+                       g("SQ_INSTS_VALU_TRANS_F64") + 2.0 * g("SQ_INSTS_VALU_FMA_F64"))
+        axis = int(sk.split(",")[1])
+        alg = sweep_flops(3, n3, axis, fused_rk=(axis == 2))
+        lines.append(f"valu {sk}: add_f64={g('SQ_INSTS_VALU_ADD_F64'):.0f}, "
+                     f"mul_f64={g('SQ_INSTS_VALU_MUL_F64'):.0f}, "
+                     f"fma_f64={g('SQ_INSTS_VALU_FMA_F64'):.0f}, "
+                     f"trans_f64={g('SQ_INSTS_VALU_TRANS_F64'):.0f}, "
+                     f"valu_all={g('SQ_INSTS_VALU'):.0f}, waves={g('SQ_WAVES'):.0f}, "
+                     f"active_inst_valu={g('SQ_ACTIVE_INST_VALU'):.0f}, "
+                     f"busy_cycles={g('SQ_BUSY_CYCLES'):.0f}, executed_f64_flop={flop:.4e}, "
+                     f"algorithmic_flop={alg:.4e}")
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n2d", type=int, default=2048)
+    ap.add_argument("--steps2d", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--fd-cells", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only (no schemes / batched / adjoint legs)")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--summarize-counters", metavar="DIR")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); sharding over several "
+              "GPUs is a design note only", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+
+    from paper_2003_09145_amd import binding as B
+    from paper_2003_09145_amd import workloads as W
+
+    B.lib()
+    prob, U, value, ms, roofline, whole = headline(args, B, W, torch)
     out = {
-        "metric": "TENO RHS cell-updates/s (256^3 FP64)",
+        "metric": METRIC,
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -156,25 +640,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D periodic Euler turbulence {args.n}^3, Mt=0.6, k0=4, "
-                               f"SSP-RK3 CFL 0.5, TENO5-LAD characteristic, global LF",
-                   "cells": ncell, "parallelism": "single GPU"},
+        "config": {"workload": f"3D periodic Euler turbulence {args.n}^3 on [0, 2pi]^3, Mt=0.6, "
+                               f"k0=4, u_rms=1, seed 0; SSP-RK3 CFL 0.5; TENO5-LAD "
+                               f"characteristic reconstruction of global-LF split fluxes",
+                   "cells": prob.ncell, "parallelism": "single GPU"},
         "roofline": roofline,
+        "step": whole,
     }
-
+    if not args.no_extras:
+        out["schemes"] = schemes_leg(args, B, W, torch)
+        out["batched"] = batched_leg(args, B, W, torch)
+        out["adjoint"] = adjoint_leg(args, B, W, torch)
     if not args.no_cpu_baseline:
-        import oracle
-        U0 = np.ascontiguousarray(U)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t0 = time.time()
-        oracle.step(prob, U0, 0.5, 0.0, float("inf"))
-        el = time.time() - t0
-        out["cpu_baseline"] = {
-            "value": 3.0 * ncell / el, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 RHS + stage updates) of the same {args.n}^3 input, "
-                      f"{el:.1f} s wall on {threads} OpenMP threads"}
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(prob, U)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -86,6 +86,10 @@ typedef struct teno_grid {
  * instead of the certified fast path (identical results, slower; for
  * verification and timing comparisons). */
 #define TENO_FLAG_LITERAL_DECISIONS 1
+/* teno_grid.flags: teno_step launches the sweep variant that accumulates the
+ * cutoff-mask digest into ctrl.digest while ctrl.want_digest is set.  Without
+ * this flag the sweeps carry no digest code and ctrl.digest is left alone. */
+#define TENO_FLAG_MASK_DIGEST 2
 
 /* Time-stepping control block.  Lives in DEVICE memory so that step loops
  * never synchronise with the host and can be captured in a HIP graph. */
@@ -125,7 +129,8 @@ int teno_ctrl_init(teno_ctrl* ctrl_dev, double t0, double t_end, double cfl,
 int teno_ctrl_replay(teno_ctrl* ctrl_dev, const teno_ctrl* recorded_dev, void* stream);
 
 /* Switch the cutoff-mask digest of later teno_step calls on (enable = 1) or
- * off, and reset it to 0 (enqueued). */
+ * off, and reset it to 0 (enqueued).  Only grids with TENO_FLAG_MASK_DIGEST
+ * accumulate it. */
 int teno_ctrl_digest(teno_ctrl* ctrl_dev, int32_t enable, void* stream);
 
 /* dUdt_dev = L(U_dev): the semi-discrete RHS of eq 2.2 summed over the axes
@@ -188,6 +193,15 @@ int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
  * ctrl.status and leaves U_dev at its value before the step. */
 int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
               void* ws_dev, size_t ws_bytes, void* stream);
+
+/* teno_step with timing marks, for profiling the launches of a step inside a
+ * longer timed region.  events: 2 * 3 * ndim hipEvent_t handles created by the
+ * caller (entries may be null); events[2 * (3 * s + d)] is recorded on
+ * `stream` right before the sweep kernel of axis d in RK stage s and
+ * events[2 * (3 * s + d) + 1] right after it.  Results are identical to
+ * teno_step. */
+int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
+                    void* ws_dev, size_t ws_bytes, void* const* events, void* stream);
 
 /* ------------------------------------------------------------------------
  * Discrete adjoint.  With the cutoff flags delta_k of eq 2.14 (hence the

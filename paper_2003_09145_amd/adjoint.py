@@ -23,6 +23,9 @@ class Recorder:
     def __init__(self, prob, device="cuda"):
         self.S = B.Solver(prob, device=device)
         self.g = self.S.g
+        # the same grid with the mask digest compiled in (finite-difference checks)
+        self.g_digest = B.grid(prob)
+        self.g_digest.flags |= B.FLAG_MASK_DIGEST
         self.device = self.S.device
         self.ws_adj = torch.empty(B.adjoint_workspace_bytes(self.g), dtype=torch.uint8,
                                   device=self.device)
@@ -37,8 +40,9 @@ class Recorder:
             B.ctrl_digest(S.ctrl, True)
         log = torch.empty((nsteps, B.CTRL_BYTES), dtype=torch.uint8, device=self.device)
         ckpt = {0: U0.clone()}
+        g = self.g_digest if digest else self.g
         for k in range(nsteps):
-            S.step(U)
+            B.teno_step(g, U, S.ctrl, S.ws)
             log[k].copy_(S.ctrl)
             if (k + 1) % seg == 0 and k + 1 < nsteps:
                 ckpt[k + 1] = U.clone()
@@ -51,9 +55,10 @@ class Recorder:
         S.init(0.0, float("inf"), 1.0)
         if digest:
             B.ctrl_digest(S.ctrl, True)
+        g = self.g_digest if digest else self.g
         for k in range(log.shape[0]):
             B.ctrl_replay(S.ctrl, log[k])
-            S.step(U)
+            B.teno_step(g, U, S.ctrl, S.ws)
         return U
 
     def backward(self, lam_T, log, ckpt, seg=20):

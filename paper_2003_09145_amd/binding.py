@@ -40,6 +40,7 @@ class TenoGrid(ctypes.Structure):
 
 
 FLAG_LITERAL_DECISIONS = 1
+FLAG_MASK_DIGEST = 2
 
 
 class TenoCtrl(ctypes.Structure):
@@ -65,7 +66,7 @@ assert CTRL_BYTES == 152
 # Every symbol declared in include/teno.h (checked by the ABI tests).
 SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_ctrl_replay", "teno_ctrl_digest",
            "teno_rhs", "teno_rhs_debug", "teno_sweep",
-           "teno_selftest_arith", "teno_step",
+           "teno_selftest_arith", "teno_step", "teno_step_timed",
            "teno_adjoint_workspace_bytes", "teno_rhs_adjoint", "teno_step_adjoint",
            "teno_batch_plan_create", "teno_batch_plan_destroy", "teno_batch_total_cells",
            "teno_batch_init", "teno_batch_step", "teno_batch_run", "teno_batch_autotune",
@@ -106,6 +107,8 @@ def lib():
         L.teno_selftest_arith.restype = ctypes.c_int
         L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step.restype = ctypes.c_int
+        L.teno_step_timed.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp, vp]
+        L.teno_step_timed.restype = ctypes.c_int
         L.teno_adjoint_workspace_bytes.argtypes = [G]
         L.teno_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.teno_rhs_adjoint.argtypes = [G, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -170,7 +173,8 @@ def grid(prob) -> TenoGrid:
     g.Bl = int(_get(prob, "Bl", 4))
     g.Bu = int(_get(prob, "Bu", 10))
     g.eps = float(_get(prob, "eps", 1e-6))
-    g.flags = FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0
+    g.flags = ((FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0) |
+               (FLAG_MASK_DIGEST if _get(prob, "mask_digest", False) else 0))
     return g
 
 
@@ -241,6 +245,19 @@ def teno_step(g, U, ctrl, ws, stream=None):
                            ws.numel() * ws.element_size(), _stream(stream)), "teno_step")
 
 
+def teno_step_timed(g, U, ctrl, ws, events, stream=None):
+    """teno_step recording events[2 * (3 * s + d)] / [... + 1] (torch.cuda.Event
+    objects, already recorded once so that they exist) around the sweep of
+    axis d in stage s."""
+    n = 2 * 3 * g.ndim
+    if len(events) != n:
+        raise TenoError(f"teno_step_timed needs {n} events")
+    arr = (ctypes.c_void_p * n)(*[e.cuda_event for e in events])
+    _check(lib().teno_step_timed(ctypes.byref(g), _ptr(U), _ptr(ctrl), _ptr(ws),
+                                 ws.numel() * ws.element_size(), arr, _stream(stream)),
+           "teno_step_timed")
+
+
 def adjoint_workspace_bytes(g: TenoGrid) -> int:
     return int(lib().teno_adjoint_workspace_bytes(ctypes.byref(g)))
 
@@ -291,8 +308,11 @@ class Solver:
     def init(self, t0=0.0, t_end=float("inf"), cfl=0.5):
         ctrl_init(self.ctrl, t0, t_end, cfl)
 
-    def step(self, U):
-        teno_step(self.g, U, self.ctrl, self.ws)
+    def step(self, U, events=None):
+        if events is None:
+            teno_step(self.g, U, self.ctrl, self.ws)
+        else:
+            teno_step_timed(self.g, U, self.ctrl, self.ws, events)
 
     def read_ctrl(self) -> TenoCtrl:
         host = self.ctrl.cpu().numpy().tobytes()

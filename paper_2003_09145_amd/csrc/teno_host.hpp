@@ -29,7 +29,7 @@ inline int validate(const teno_grid* g) {
         if (g->Bl < 0 || g->Bu > 20 || g->Bl > g->Bu || !(g->H > 0.0)) return TENO_ERR_ARG;
     }
     if (!(g->eps > 0.0)) return TENO_ERR_ARG;
-    if (g->flags & ~TENO_FLAG_LITERAL_DECISIONS) return TENO_ERR_ARG;
+    if (g->flags & ~(TENO_FLAG_LITERAL_DECISIONS | TENO_FLAG_MASK_DIGEST)) return TENO_ERR_ARG;
     return TENO_OK;
 }
 

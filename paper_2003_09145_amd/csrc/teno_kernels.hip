@@ -27,6 +27,9 @@ namespace teno {
 constexpr int kMaxLdsPerBlock = 64 * 1024;
 constexpr int kFacesPerChunk = 64;
 constexpr int kCellsPerChunk = 63;
+// blocks of the LF-speed reduction: each writes one partial (3 maxima and a
+// non-physical flag), reduced afterwards by a single block (no atomics)
+constexpr int kAlphaBlocks = 2048;
 
 // Per-launch description of one sweep.
 struct SweepArgs {
@@ -74,7 +77,7 @@ __device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
-template <int ND, int DIR, int W>
+template <int ND, int DIR, int W, bool DIGEST>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
@@ -138,6 +141,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     __syncthreads();
 
     // ---- numerical flux at this lane's face ----------------------------------
+    // the digest is wanted or not for the whole launch (a uniform branch); the
+    // plain variant carries no digest code at all
+    const bool want_digest =
+        DIGEST && A.digest != nullptr && (A.ctrl == nullptr || A.ctrl->want_digest);
     unsigned long long sig = 0ull;
     if (valid) {
         const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of cell i-2
@@ -149,17 +156,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         double Fh[NC];
         uint32_t masks = 0;
-        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh, &masks);
+        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
+                           want_digest ? &masks : nullptr);
 #pragma unroll
         for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
-        // the key names the step and stage as well as the face, so masks that
-        // move in time past a face change the digest
-        const uint64_t when = (A.ctrl != nullptr ? 3ull * (uint64_t)A.ctrl->nsteps : 0ull) +
-                              (uint64_t)A.stage;
-        sig = mask_hash(mask_hash(when) ^ ((uint64_t)A.axis << 60) ^
-                        ((uint64_t)(col * A.ftot + Fc) << 30) ^ masks);
+        if (want_digest) {
+            // the key names the step and stage as well as the face, so masks
+            // that move in time past a face change the digest
+            const uint64_t when =
+                (A.ctrl != nullptr ? 3ull * (uint64_t)A.ctrl->nsteps : 0ull) + (uint64_t)A.stage;
+            sig = mask_hash(mask_hash(when) ^ ((uint64_t)A.axis << 60) ^
+                            ((uint64_t)(col * A.ftot + Fc) << 30) ^ masks);
+        }
     }
-    if (A.digest != nullptr && (A.ctrl == nullptr || A.ctrl->want_digest)) {
+    if (want_digest) {
         // a face shared by two chunks (lane 63 here, lane 0 of the next) counts once
         unsigned long long v = (valid && (lane < 63 || F == A.ftot - 1)) ? sig : 0ull;
 #pragma unroll
@@ -202,12 +212,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 }
 
 // ---- global Lax-Friedrichs speeds: alpha_d = max (|u_d| + c) -------------
+// Pass 1 (k_alpha): every block reduces its cells and writes part[4 b + k]
+// (k < 3: the maxima, 0 for absent axes; k = 3: 1.0 if the block saw a cell
+// with rho <= 0, p <= 0 or a non-finite sound speed).  Pass 2
+// (reduce_partials, inside the consumer kernel): one 256-thread block.
 template <int ND>
 __global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ U, int64_t ncell,
-                                               double gamma,
-                                               unsigned long long* __restrict__ abits,
-                                               int32_t* __restrict__ status) {
+                                               double gamma, double* __restrict__ part) {
     constexpr int NC = ND + 2;
+    __shared__ double red[4][4];
     double amax[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) amax[k] = 0.0;
@@ -236,45 +249,98 @@ __global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ U, int
             if (s > amax[k]) amax[k] = s;
         }
     }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v4[4] = {0.0, 0.0, 0.0, bad ? 1.0 : 0.0};
 #pragma unroll
-    for (int k = 0; k < ND; ++k) {
-        double v = amax[k];
+    for (int k = 0; k < ND; ++k) v4[k] = amax[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = v4[k];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off, 64);
             if (o > v) v = o;
         }
-        if ((threadIdx.x & 63) == 0 && v > 0.0)
-            atomicMax(&abits[k], (unsigned long long)__double_as_longlong(v));
+        if (lane == 0) red[wv][k] = v;
     }
-    if (bad && status != nullptr) atomicMax(status, (int32_t)TENO_ERR_NONPHYSICAL);
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (red[w][k] > v) v = red[w][k];
+        part[4 * (int64_t)blockIdx.x + k] = v;
+    }
 }
 
-__global__ void k_zero_scratch(unsigned long long* abits, int32_t* status) {
-    if (threadIdx.x < 3) abits[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0 && status != nullptr) *status = 0;
+// Maximum of the nblk partials (call from every thread of a 256-thread
+// block); out[0..2] the speeds, out[3] > 0 if any cell was non-physical.
+__device__ void reduce_partials(const double* __restrict__ part, int nblk, double out[4]) {
+    __shared__ double red[4][4];
+    double v4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double x = part[4 * b + k];
+            if (x > v4[k]) v4[k] = x;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = v4[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, 64);
+            if (o > v) v = o;
+        }
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = red[0][k];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (red[w][k] > v) v = red[w][k];
+        out[k] = v;
+    }
 }
 
-__global__ void k_copy_alpha(const unsigned long long* abits, const double* alpha_in,
-                             double* alpha_used, double* alpha_out) {
+// Speeds used by teno_rhs: the frozen ones, or the reduced partials (with
+// the non-physical flag written to status).
+__global__ __launch_bounds__(256) void k_copy_alpha(const double* part, int nblk,
+                                                    const double* alpha_in, double* alpha_used,
+                                                    double* alpha_out, int32_t* status) {
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    if (alpha_in == nullptr) reduce_partials(part, nblk, r);
     const int k = threadIdx.x;
     if (k < 3) {
-        const double a = alpha_in ? alpha_in[k] : __longlong_as_double((long long)abits[k]);
+        const double a = alpha_in ? alpha_in[k] : r[k];
         alpha_used[k] = a;
         if (alpha_out) alpha_out[k] = a;
     }
+    if (k == 0 && status != nullptr) *status = (r[3] > 0.0) ? TENO_ERR_NONPHYSICAL : TENO_OK;
 }
 
-// Stage bookkeeping of teno_step (one thread).
-__global__ void k_stage_begin(teno_ctrl* ctrl, const unsigned long long* abits, int stage,
-                              int ndim, double dx0, double dx1, double dx2) {
+// Stage bookkeeping of teno_step (one 256-thread block): reduce the speeds
+// of the stage input, flag a non-physical input (sticky), and at stage 0
+// set dt from eq dt1 / dt2 (3D: the harmonic form) clipped to t_end.
+__global__ __launch_bounds__(256) void k_stage_begin(teno_ctrl* ctrl, const double* part,
+                                                     int nblk, int stage, int ndim, double dx0,
+                                                     double dx1, double dx2) {
+    double r[4];
+    reduce_partials(part, nblk, r);
     if (threadIdx.x != 0) return;
+    const bool bad = r[3] > 0.0;
     if (stage == 0) {
         ctrl->active = 0;
         if (ctrl->status != 0 || !(ctrl->t < ctrl->t_end)) return;
+        if (bad) {
+            ctrl->status = TENO_ERR_NONPHYSICAL;
+            return;
+        }
         if (!ctrl->replay) {
-            double a[3];
-            for (int k = 0; k < 3; ++k) a[k] = __longlong_as_double((long long)abits[k]);
+            const double* a = r;
             double dt;
             if (ndim == 1) {
                 dt = cr_div(ctrl->cfl * dx0, a[0]);
@@ -292,13 +358,13 @@ __global__ void k_stage_begin(teno_ctrl* ctrl, const unsigned long long* abits, 
         ctrl->active = 1;
     } else {
         if (!ctrl->active) return;
+        if (bad) ctrl->status = TENO_ERR_NONPHYSICAL;
         if (ctrl->status != 0) {
             ctrl->active = 0;
             return;
         }
         if (!ctrl->replay)
-            for (int k = 0; k < 3; ++k)
-                ctrl->alpha[stage][k] = __longlong_as_double((long long)abits[k]);
+            for (int k = 0; k < 3; ++k) ctrl->alpha[stage][k] = r[k];
     }
 }
 
@@ -360,11 +426,10 @@ __global__ void k_selftest_arith(const double* a, const double* b, double* q, do
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-struct Scratch {  // small device area at the end of the workspace
-    unsigned long long abits[4];
+struct Scratch {  // device area at the end of the workspace
+    double part[4 * kAlphaBlocks];  // LF-speed partials of k_alpha
     double alpha_used[4];
-    int32_t status;
-    int32_t pad[7];
+    int32_t pad[8];
 };
 
 static int64_t ncell_of(const teno_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
@@ -382,7 +447,7 @@ static Scratch* scratch_of(const teno_grid* g, void* ws) {
 }
 
 template <int ND, int DIR>
-static hipError_t launch_sweep_t(SweepArgs A, hipStream_t st) {
+static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;
     const size_t per_wave =
@@ -390,11 +455,19 @@ static hipError_t launch_sweep_t(SweepArgs A, hipStream_t st) {
     const size_t table = 24 * sizeof(double);
     if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
         const int64_t blocks = (A.nchunks + 3) / 4;
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 4>), dim3((unsigned)blocks), dim3(256),
-                           table + 4 * per_wave, st, A);
+        if (digest)
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true>), dim3((unsigned)blocks), dim3(256),
+                               table + 4 * per_wave, st, A);
+        else
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false>), dim3((unsigned)blocks), dim3(256),
+                               table + 4 * per_wave, st, A);
     } else {
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 1>), dim3((unsigned)A.nchunks), dim3(64),
-                           table + per_wave, st, A);
+        if (digest)
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, true>), dim3((unsigned)A.nchunks), dim3(64),
+                               table + per_wave, st, A);
+        else
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false>), dim3((unsigned)A.nchunks), dim3(64),
+                               table + per_wave, st, A);
     }
     return hipGetLastError();
 }
@@ -432,26 +505,30 @@ static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStre
     A.ftot = lines_per_col * (n + 1);
     const int64_t chunks_per_col = (A.ftot - 1 + kCellsPerChunk - 1) / kCellsPerChunk;
     A.nchunks = chunks_per_col * A.ncols;
+    const bool digest = A.digest != nullptr && (g->flags & TENO_FLAG_MASK_DIGEST) != 0;
     switch (g->ndim * 4 + dir) {
-        case 4: return launch_sweep_t<1, 0>(A, st);
-        case 8: return launch_sweep_t<2, 0>(A, st);
-        case 9: return launch_sweep_t<2, 1>(A, st);
-        case 12: return launch_sweep_t<3, 0>(A, st);
-        case 13: return launch_sweep_t<3, 1>(A, st);
-        case 14: return launch_sweep_t<3, 2>(A, st);
+        case 4: return launch_sweep_t<1, 0>(A, digest, st);
+        case 8: return launch_sweep_t<2, 0>(A, digest, st);
+        case 9: return launch_sweep_t<2, 1>(A, digest, st);
+        case 12: return launch_sweep_t<3, 0>(A, digest, st);
+        case 13: return launch_sweep_t<3, 1>(A, digest, st);
+        case 14: return launch_sweep_t<3, 2>(A, digest, st);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_alpha(const teno_grid* g, const double* U, unsigned long long* abits,
-                               int32_t* status, hipStream_t st) {
+static int alpha_blocks(const teno_grid* g) {
+    const int64_t b = (ncell_of(g) + 255) / 256;
+    return (int)(b < kAlphaBlocks ? b : kAlphaBlocks);
+}
+
+static hipError_t launch_alpha(const teno_grid* g, const double* U, double* part, hipStream_t st) {
     const int64_t nc = ncell_of(g);
-    int64_t blocks = (nc + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    const int blocks = alpha_blocks(g);
     switch (g->ndim) {
-        case 1: hipLaunchKernelGGL(k_alpha<1>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
-        case 2: hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
-        case 3: hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(256), 0, st, U, nc, g->gamma, abits, status); break;
+        case 1: hipLaunchKernelGGL(k_alpha<1>, dim3(blocks), dim3(256), 0, st, U, nc, g->gamma, part); break;
+        case 2: hipLaunchKernelGGL(k_alpha<2>, dim3(blocks), dim3(256), 0, st, U, nc, g->gamma, part); break;
+        case 3: hipLaunchKernelGGL(k_alpha<3>, dim3(blocks), dim3(256), 0, st, U, nc, g->gamma, part); break;
     }
     return hipGetLastError();
 }
@@ -464,12 +541,11 @@ static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const d
         return TENO_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     Scratch* S = scratch_of(g, ws);
-    hipLaunchKernelGGL(k_zero_scratch, dim3(1), dim3(64), 0, st, S->abits, status);
     if (alpha_in == nullptr) {
-        if (launch_alpha(g, U, S->abits, status, st) != hipSuccess) return TENO_ERR_DEVICE;
+        if (launch_alpha(g, U, S->part, st) != hipSuccess) return TENO_ERR_DEVICE;
     }
-    hipLaunchKernelGGL(k_copy_alpha, dim3(1), dim3(64), 0, st, S->abits, alpha_in,
-                       S->alpha_used, alpha_out);
+    hipLaunchKernelGGL(k_copy_alpha, dim3(1), dim3(256), 0, st, S->part, alpha_blocks(g), alpha_in,
+                       S->alpha_used, alpha_out, status);
     int64_t dump_off = 0;
     for (int d = 0; d < g->ndim; ++d) {
         SweepArgs A;
@@ -579,8 +655,10 @@ int teno_sweep(const teno_grid* g, int32_t axis, const double* U, const double* 
     return launch_sweep(g, axis, A, (hipStream_t)stream) == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
 }
 
-int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
-              void* stream) {
+}  // extern "C"
+
+static int step_impl(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
+                     void* const* events, void* stream) {
     if (validate(g) != TENO_OK || U == nullptr || ctrl == nullptr || ws == nullptr ||
         ws_bytes < workspace_bytes_impl(g))
         return TENO_ERR_ARG;
@@ -593,11 +671,9 @@ int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t w
     const double* stage_in[3] = {U, U1, U2};
     double* stage_out[3] = {U1, U2, U};
     for (int s = 0; s < 3; ++s) {
-        hipLaunchKernelGGL(k_zero_scratch, dim3(1), dim3(64), 0, st, S->abits, (int32_t*)nullptr);
-        if (launch_alpha(g, stage_in[s], S->abits, &ctrl->status, st) != hipSuccess)
-            return TENO_ERR_DEVICE;
-        hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(64), 0, st, ctrl, S->abits, s, g->ndim,
-                           g->dx[0], g->dx[1], g->dx[2]);
+        if (launch_alpha(g, stage_in[s], S->part, st) != hipSuccess) return TENO_ERR_DEVICE;
+        hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(256), 0, st, ctrl, S->part, alpha_blocks(g),
+                           s, g->ndim, g->dx[0], g->dx[1], g->dx[2]);
         for (int d = 0; d < g->ndim; ++d) {
             SweepArgs A;
             memset(&A, 0, sizeof(A));
@@ -615,11 +691,29 @@ int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t w
                 A.Un = U;
                 A.Uout = stage_out[s];
             }
+            void* ev0 = events ? events[2 * (3 * s + d)] : nullptr;
+            void* ev1 = events ? events[2 * (3 * s + d) + 1] : nullptr;
+            if (ev0 != nullptr && hipEventRecord((hipEvent_t)ev0, st) != hipSuccess)
+                return TENO_ERR_DEVICE;
             if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;
+            if (ev1 != nullptr && hipEventRecord((hipEvent_t)ev1, st) != hipSuccess)
+                return TENO_ERR_DEVICE;
         }
     }
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctrl);
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
+}
+
+extern "C" {
+
+int teno_step(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
+              void* stream) {
+    return step_impl(g, U, ctrl, ws, ws_bytes, nullptr, stream);
+}
+
+int teno_step_timed(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
+                    void* const* events, void* stream) {
+    return step_impl(g, U, ctrl, ws, ws_bytes, events, stream);
 }
 
 }  // extern "C"

@@ -160,7 +160,10 @@ def test_trajectory_gradient_and_checkpoint_invariance(torch, B, orc):
 
 def test_gradient_finite_differences_with_digest(torch, B):
     # d J / d rho0 (u0, p0 fixed) against central differences h = 1e-6 with
-    # replayed dt and speeds, at cells whose cutoff masks do not change
+    # replayed dt and speeds, at cells whose cutoff masks do not change.  Bar:
+    # 1e-6 relative where the gradient is at least 10% of its largest value,
+    # else 1e-7 of that value (the difference quotient's rounding floor grows
+    # as 1/h and sits near 2e-8 of it here)
     N, steps, ncheck = 2048, 100, 16
     prob, U0, Utarget = _loss_setup(N)
     dx = prob.dx[0]
@@ -186,6 +189,7 @@ def test_gradient_finite_differences_with_digest(torch, B):
     x = prob.centres(0)
     cells = rng.choice(np.nonzero(x >= -4.0)[0], 64, replace=False)
     h = 1e-6
+    gmax = float(np.abs(grad_rho).max())
     checked = skipped = 0
     for i in cells:
         if checked == ncheck:
@@ -201,8 +205,35 @@ def test_gradient_finite_differences_with_digest(torch, B):
             continue
         fd = (Jp - Jm) / (2 * h)
         ad = grad_rho[0, 0, i]
-        assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12, (i, fd, ad)
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 0.1 * gmax), (i, fd, ad, gmax)
         checked += 1
     print(f"[adjoint] FD check: {checked} cells within 1e-6, {skipped} skipped (mask change)",
           flush=True)
     assert checked == ncheck
+
+
+def test_digest_variant_identical_and_flag_required(torch, B):
+    prob, U = W.shu_osher(300)
+    rec = _recorder(B, prob)
+    Ud = torch.from_numpy(U.copy()).cuda()
+    U1, log1, _ = rec.forward(Ud, 5, 0.5, digest=True)
+    d1 = rec.digest()
+    U2, log2, _ = rec.forward(Ud, 5, 0.5, digest=False)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    assert np.array_equal(_log_host(B, log1)[0], _log_host(B, log2)[0])
+    assert np.array_equal(_log_host(B, log1)[1], _log_host(B, log2)[1])
+    assert d1 != 0
+    # a grid without TENO_FLAG_MASK_DIGEST never touches the digest
+    S = B.Solver(prob)
+    S.init(0.0, float("inf"), 0.5)
+    B.ctrl_digest(S.ctrl, True)
+    u = Ud.clone()
+    S.step(u)
+    torch.cuda.synchronize()
+    assert S.read_ctrl().digest == 0 and torch.equal(u, _first_step(rec, Ud))
+
+
+def _first_step(rec, Ud):
+    U1, _, _ = rec.forward(Ud, 1, 0.5)
+    return U1
