@@ -152,6 +152,13 @@ struct DecisionConsts {
     int32_t literal;       // 1: evaluate every decision with the literal formula
     int32_t need_m;        // 1: the ladder index is wanted (decision dumps)
     int32_t pad_;
+    // Smooth-stencil bound: when tau <= smooth_t (min_k beta_k + eps), every
+    // chi~_k = tau / (beta_k + eps) is at most smooth_t (to rounding), so each
+    // gamma_k of eq 2.8 lies in [1, (1 + smooth_t)^6] and every chi_k is at
+    // least 1 / (1 + 2 (1 + smooth_t)^6), which the host chooses above the
+    // largest cutoff ct_hi: all three stencils are kept, whatever the ladder
+    // index.  Negative: no such bound (never satisfied).
+    double smooth_t;
 };
 
 // Relative margin inside which an approximate decision value is not trusted
@@ -231,9 +238,13 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
     } else {
         bool sure = K.literal == 0;
         uint32_t m = 0, mask = 7u;
-        if (sure) {
+        const double tau = fabs(beta2 - beta0);
+        double bmin = beta0 < beta1 ? beta0 : beta1;
+        bmin = beta2 < bmin ? beta2 : bmin;
+        if (sure && K.need_m == 0 && tau <= K.smooth_t * (bmin + S.eps)) {
+            // smooth stencil: all kept (no reciprocal, no gamma_k)
+        } else if (sure) {
             // Approximate gamma_k (eq 2.8) from approximate chi~_k = tau / (beta_k + eps).
-            const double tau = fabs(beta2 - beta0);
             const double t0 = tau * rcp_nr(beta0 + S.eps);
             const double t1 = tau * rcp_nr(beta1 + S.eps);
             const double t2 = tau * rcp_nr(beta2 + S.eps);

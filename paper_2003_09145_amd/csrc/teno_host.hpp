@@ -2,6 +2,8 @@
 // argument validation and the per-launch scheme / decision constants.
 #pragma once
 
+#include <cmath>
+
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -63,19 +65,34 @@ inline const double kLadderHost[21] = {1e0,   1e-1,  1e-2,  1e-3,  1e-4,  1e-5, 
                                        1e-7,  1e-8,  1e-9,  1e-10, 1e-11, 1e-12, 1e-13,
                                        1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
 
+// Largest T with 1 / (1 + 2 (1 + T)^6) >= ct (1 + 2^-30), shrunk by 2^-30:
+// stencils whose chi~_k are all <= T keep every candidate for any cutoff up
+// to ct (the rounding of the literal evaluation is far inside both
+// margins).  -1 when ct leaves no such T.
+inline double smooth_bound(double ct) {
+    if (!(ct > 0.0)) return -1.0;
+    const double g = (1.0 / (ct * (1.0 + 0x1p-30)) - 1.0) / 2.0;  // bound on (1 + T)^6
+    if (!(g > 1.0)) return -1.0;
+    const double T = (std::pow(g, 1.0 / 6.0) - 1.0) * (1.0 - 0x1p-30);
+    return T > 0.0 ? T : -1.0;
+}
+
 inline DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
     DecisionConsts K;
     memset(&K, 0, sizeof(K));
     K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
     K.need_m = need_m ? 1 : 0;
     for (int j = 0; j < kMaxThr; ++j) K.xthr[j] = -1.0;
+    K.smooth_t = -1.0;
     if (g->scheme == TENO_SCHEME_FIXED_CT) {
         K.ct_hi = K.ct_lo = g->ct_fixed;
+        K.smooth_t = smooth_bound(K.ct_hi);
         return K;
     }
     if (g->scheme != TENO_SCHEME_LAD) return K;
     K.ct_hi = kLadderHost[g->Bl];
     K.ct_lo = kLadderHost[g->Bu];
+    K.smooth_t = smooth_bound(K.ct_hi);
     K.nthr = g->Bu - g->Bl;
     if (K.nthr > kMaxThr) {  // more rungs than the fast path holds: literal decisions
         K.literal = 1;

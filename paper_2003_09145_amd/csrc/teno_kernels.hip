@@ -77,7 +77,10 @@ __device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
-template <int ND, int DIR, int W, bool DIGEST>
+// CAPC: the stencil-buffer stride when it is known at compile time (it is
+// ext_cap_for(n) = 74 for every n >= 63), so that every LDS stencil read is a
+// per-lane base plus an immediate offset; 0: taken from A.ext_cap.
+template <int ND, int DIR, int W, bool DIGEST, int CAPC>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         k = chunk / A.ncols;
     }
     const int64_t colbase = col * A.col_step;
-    const int cap = A.ext_cap;
+    const int cap = CAPC ? CAPC : A.ext_cap;
     double* omega = smem;  // 24 doubles: eq 2.15 weights per cutoff mask
     const int per_wave = (cap * NV > 64 * NC) ? cap * NV : 64 * NC;
     double* ext = smem + 24 + (size_t)wave * per_wave;
@@ -114,9 +117,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t F = F0 + lane;
     const bool valid = wave_ok && F < A.ftot;
     const int64_t Fc = valid ? F : F0;
-    const int64_t bl = Fc / np1;            // line of this lane's face
-    const int64_t phi = Fc - bl * np1;      // face index in the line (i + 1)
-    const int64_t e_lo = F0 + 5 * (F0 / np1);
+    // line and in-line index of this lane's face, from those of F0 (uniform)
+    // with a 32-bit step
+    const int64_t bl0 = F0 / np1;
+    const int phi0 = (int)(F0 - bl0 * np1);
+    const int tq = phi0 + (int)(Fc - F0);
+    const int wraps = tq / (int)np1;
+    const int64_t bl = bl0 + wraps;                        // line of this lane's face
+    const int64_t phi = tq - wraps * (int)np1;             // face index in the line (i + 1)
+    const int64_t e_lo = F0 + 5 * bl0;
     int64_t Flast = F0 + 63;
     if (Flast > A.ftot - 1) Flast = A.ftot - 1;
     const int64_t e_hi = Flast + 5 * (Flast / np1) + 6;
@@ -125,10 +134,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     // ---- stage per-cell quantities of the ext cells [e_lo, e_hi) ----------
     const double alpha = A.alpha[DIR];
     const double gm1 = A.sch.gamma - 1.0;
+    const int64_t be0 = e_lo / np6;                 // line of the first ext cell (uniform)
+    const int je0 = (int)(e_lo - be0 * np6);
     for (int idx = lane; idx < count; idx += 64) {
-        const int64_t e = e_lo + idx;
-        const int64_t b = e / np6;
-        const int j = (int)(e - b * np6) - 3;
+        const int jq = je0 + idx;
+        const int bw = jq / (int)np6;
+        const int64_t b = be0 + bw;
+        const int j = jq - bw * (int)np6 - 3;
         bool flip;
         const int src = ghost_src(A.bc, n, j, &flip);
         const int64_t cell = colbase + b * A.line_step + (int64_t)src * A.stride;
@@ -450,23 +462,28 @@ template <int ND, int DIR>
 static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;
+    constexpr int kCapLong = 74;  // ext_cap_for(n) for every n >= 63
     const size_t per_wave =
         (size_t)((A.ext_cap * NV > 64 * NC) ? A.ext_cap * NV : 64 * NC) * sizeof(double);
     const size_t table = 24 * sizeof(double);
-    if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
+    if (!digest && A.ext_cap == kCapLong) {
+        const int64_t blocks = (A.nchunks + 3) / 4;
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong>), dim3((unsigned)blocks),
+                           dim3(256), table + 4 * per_wave, st, A);
+    } else if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
         const int64_t blocks = (A.nchunks + 3) / 4;
         if (digest)
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true>), dim3((unsigned)blocks), dim3(256),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true, 0>), dim3((unsigned)blocks), dim3(256),
                                table + 4 * per_wave, st, A);
         else
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false>), dim3((unsigned)blocks), dim3(256),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, 0>), dim3((unsigned)blocks), dim3(256),
                                table + 4 * per_wave, st, A);
     } else {
         if (digest)
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, true>), dim3((unsigned)A.nchunks), dim3(64),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, true, 0>), dim3((unsigned)A.nchunks), dim3(64),
                                table + per_wave, st, A);
         else
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false>), dim3((unsigned)A.nchunks), dim3(64),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, 0>), dim3((unsigned)A.nchunks), dim3(64),
                                table + per_wave, st, A);
     }
     return hipGetLastError();

@@ -431,3 +431,28 @@ def test_nonphysical_state_is_flagged(orc):
         if st:
             break
     assert st == 3
+
+
+def test_smooth_stencils_keep_every_candidate(orc):
+    # If every chi~_k = tau / (beta_k + eps) is at most T, gamma_k lies in
+    # [1, (1 + T)^6] (eq 2.8), so each chi_k >= 1 / (1 + 2 (1 + T)^6); with T
+    # chosen so that this exceeds the largest cutoff 1e-4 no stencil is cut
+    # (eq 2.14), whatever C_T eq 3.1-3.4 picks.  The GPU decision path skips
+    # the ladder on such stencils; the oracle must agree on every one.
+    ct = 1e-4
+    T = ((1.0 / ct - 1.0) / 2.0) ** (1.0 / 6.0) - 1.0
+    assert 1.0 / (1.0 + 2.0 * (1.0 + T) ** 6) >= ct * (1 - 1e-12)
+    rng = np.random.default_rng(17)
+    fixed = {"ndim": 1, "n": [8], "dx": [1.0], "bc": "periodic", "scheme": "fixed_ct",
+             "ct_fixed": ct}
+    hits = 0
+    for trial in range(4000):
+        scale = 10.0 ** rng.uniform(-4, 2)
+        v = scale * (rng.normal(size=5) + rng.uniform(-2, 2) * np.arange(5))
+        f, m, mask, tr = orc.rec(v, trace=True)
+        if tr["x"] > T:
+            continue
+        hits += 1
+        assert mask == 7, (v, tr)
+        assert orc.rec(v, prob=fixed)[2] == 7, v
+    assert hits > 500
