@@ -123,9 +123,10 @@ def load_traffic(kernel: str):
             name, rest = line[len("kernel "):].split(":", 1)
             kv = dict(x.strip().split("=") for x in rest.split(","))
             vals[name.strip()] = kv
-    if sha != sources_sha() or kernel not in vals:
+    names = [k for k in vals if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
+    if sha != sources_sha() or len(names) != 1:
         return None
-    kv = vals[kernel]
+    kv = vals[names[0]]
     return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
 
 
@@ -178,7 +179,7 @@ def headline(args, B, W, torch):
     fused = dom == 2
     flops = sweep_flops(3, n3, dom, fused_rk=fused)
     achieved = flops / (per_axis[dom] * 1e-3) / 1e12
-    kname = f"k_sweep<3,{dom},4>"
+    kname = f"k_sweep<3,{dom},4,false>"  # the plain (digest-free) instantiation
     traffic = load_traffic(kname)
     alg_bytes = sweep_bytes(3, n3, dom, fused_rk=fused)
     roofline = {
@@ -542,20 +543,21 @@ def summarize_counters(d):
         "# HBM traffic and FP64 VALU counters of the 3D sweep kernels, 256^3 turbulence",
         "# (k_sweep<3,d,4>: axis d; axis z carries the fused RK stage update)",
         "#",
-        "# commands (from the repository root, after cd /tmp && export TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc/fetch -o fetch -- "
+        "# commands (from the repository root, after cd /tmp && export TMPDIR=/tmp; $OUT is any",
+        "# output directory):",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o fetch -- "
         "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc/write -o write -- "
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o write -- "
         "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
         "#   rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 "
         "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVES "
-        "--output-format csv -d gpurun_out/pmc/valu -o valu -- python3 bench.py --steps 5 "
+        "--output-format csv -d $OUT/valu -o valu -- python3 bench.py --steps 5 "
         "--warmup 1 --no-cpu-baseline --no-extras",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc/calf -o calf -- "
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/calf -o calf -- "
         "python3 bench.py --copy-calibration",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc/calw -o calw -- "
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/calw -o calw -- "
         "python3 bench.py --copy-calibration",
-        "#   python3 bench.py --summarize-counters gpurun_out/pmc",
+        "#   python3 bench.py --summarize-counters $OUT",
         "#",
         f"# copy calibration: a plain {COPY_BYTES} B device copy reads FETCH_SIZE = {cf_kib:.0f} KiB "
         f"and WRITE_SIZE = {cw_kib:.0f} KiB per dispatch",
