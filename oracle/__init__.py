@@ -28,7 +28,7 @@ _SRC = os.path.join(_HERE, "teno_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
-SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2}
+SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
 
 
 class OrParams(ctypes.Structure):
@@ -44,6 +44,10 @@ class OrParams(ctypes.Structure):
         ("Bl", ctypes.c_int32),
         ("Bu", ctypes.c_int32),
         ("eps", ctypes.c_double),
+        ("a1", ctypes.c_double),
+        ("a2", ctypes.c_double),
+        ("cr", ctypes.c_double),
+        ("xi", ctypes.c_double),
     ]
 
 
@@ -125,6 +129,10 @@ def params(prob) -> OrParams:
     p.Bl = int(_get(prob, "Bl", 4))
     p.Bu = int(_get(prob, "Bu", 10))
     p.eps = float(_get(prob, "eps", 1e-6))
+    p.a1 = float(_get(prob, "a1", 10.5))   # TENO5-A parameters (Sec. 2, Sec. 4)
+    p.a2 = float(_get(prob, "a2", 3.5))
+    p.cr = float(_get(prob, "cr", 0.25))
+    p.xi = float(_get(prob, "xi", 1e-3))
     return p
 
 

@@ -45,12 +45,15 @@ typedef struct {
     int32_t n[3];       /* cells along x, y, z (unused axes: 1)              */
     double dx[3];       /* uniform spacing per axis                         */
     int32_t bc[3];      /* 0 periodic, 1 zero-gradient, 2 reflecting        */
-    int32_t scheme;     /* 0 TENO5-LAD, 1 TENO5 fixed C_T, 2 linear upwind5 */
+    int32_t scheme;     /* 0 TENO5-LAD, 1 TENO5 fixed C_T, 2 linear upwind5,
+                           3 TENO5-A (adaptive C_T of eq 2.16-2.18)         */
     double gamma;       /* ratio of specific heats                          */
     double ct_fixed;    /* C_T of scheme 1                                  */
     double H;           /* LAD intensity threshold (Sec. 3, eq 3.2)         */
     int32_t Bl, Bu;     /* LAD magnitude bounds (Sec. 3, eq 3.1)            */
     double eps;         /* epsilon of eq 2.8 / eq 3.2                       */
+    double a1, a2;      /* TENO5-A: alpha_1, alpha_2 of eq 2.16             */
+    double cr, xi;      /* TENO5-A: C_r of eq 2.17, xi of eq 2.18           */
 } OrParams;
 
 }  // extern "C"
@@ -176,6 +179,38 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
         ct = POW10NEG[m];
     } else if (P.scheme == 1) {
         ct = P.ct_fixed;
+    } else if (P.scheme == 3) {
+        /* TENO5-A, eq 2.16-2.18.  The sensor of eq 2.18 at the stencil points
+         * j = i-1, i, i+1 uses df_{j+1/2} = f_{j+1} - f_j and df_{j-1/2}; its
+         * denominator is read as df_{j+1/2}^2 + df_{j-1/2}^2 (the printed
+         * formula repeats df_{i+1/2}).  epsilon = 0.9 C_r / (1 - 0.9 C_r) xi^2. */
+        double epsA = ((0.9 * P.cr) / (1.0 - 0.9 * P.cr)) * (P.xi * P.xi);
+        double df[4] = {b - a, c - b, d - c, e - d};
+        double eta[3];
+        for (int j = 0; j < 3; ++j) {
+            double dm = df[j], dp = df[j + 1];
+            eta[j] = (2.0 * std::fabs(dp * dm) + epsA) / ((dp * dp + dm * dm) + epsA);
+        }
+        /* eq 2.17: eta_{i+1/2} = min of the three, m = 1 - min(1, eta / C_r) */
+        double eh = eta[0];
+        if (eta[1] < eh) eh = eta[1];
+        if (eta[2] < eh) eh = eta[2];
+        double q = eh / P.cr;
+        double mA = 1.0 - (q < 1.0 ? q : 1.0);
+        /* eq 2.16: g(m) = (1 - m)^4 (1 + 4 m), beta = alpha_1 - alpha_2 (1 - g),
+         * C_T = 10^-floor(beta) */
+        double om = 1.0 - mA;
+        double om2 = om * om;
+        double g = (om2 * om2) * (1.0 + 4.0 * mA);
+        double bA = P.a1 - P.a2 * (1.0 - g);
+        /* a NaN sensor (non-finite stencil) takes the largest cutoff */
+        if (bA >= 0.0)
+            m = (int)std::floor(bA);
+        else
+            m = (int)std::floor(P.a1 - P.a2);
+        x = eh;
+        theta = bA;
+        ct = POW10NEG[m];
     }
     /* Cutoff, eq 2.14 (a tie chi_k == C_T keeps the stencil). */
     int mask = 0;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libteno.so")
 
 OK, ERR_ARG, ERR_DEVICE, ERR_NONPHYSICAL = 0, 1, 2, 3
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
-SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2}
+SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
 
 
 class TenoGrid(ctypes.Structure):

@@ -28,12 +28,16 @@ class Problem:
     dx: List[float]
     bc: List[str]
     gamma: float = 1.4
-    scheme: str = "lad"          # "lad", "fixed_ct", "linear5"
+    scheme: str = "lad"          # "lad", "fixed_ct", "linear5", "teno5a"
     ct_fixed: float = 1e-7       # C_T of the fixed-cutoff TENO5 (Sec. 4 default)
     H: float = 10.0              # LAD parameters (Sec. 4)
     Bl: int = 4
     Bu: int = 10
     eps: float = 1e-6            # epsilon of eq 2.8 (Sec. 2)
+    a1: float = 10.5             # TENO5-A parameters (eq 2.16-2.18, Sec. 4 defaults)
+    a2: float = 3.5
+    cr: float = 0.25
+    xi: float = 1e-3
     x0: List[float] = dataclasses.field(default_factory=lambda: [0.0, 0.0, 0.0])
 
     @property

@@ -59,8 +59,11 @@ def test_table1_linear_advection(orc):
     for N, ref, order in tab:
         u, e = _advect(orc, int(N), lambda dx: dx ** (5.0 / 3.0))
         ulin, _ = _advect(orc, int(N), lambda dx: dx ** (5.0 / 3.0), scheme="linear5")
-        # LAD keeps every stencil on this smooth input: identical to Upwind5.
+        ua, _ = _advect(orc, int(N), lambda dx: dx ** (5.0 / 3.0), scheme="teno5a")
+        # LAD and TENO5-A keep every stencil on this smooth input: identical
+        # to Upwind5 (the table's columns coincide).
         assert np.array_equal(u, ulin)
+        assert np.array_equal(ua, ulin)
         # The literal dt = dx^(5/3) run sits 3-5% above the printed errors.
         assert abs(e / ref - 1.0) < 0.06, (N, e, ref)
         l2.append(e)
@@ -456,3 +459,58 @@ def test_smooth_stencils_keep_every_candidate(orc):
         assert mask == 7, (v, tr)
         assert orc.rec(v, prob=fixed)[2] == 7, v
     assert hits > 500
+
+
+# --------------------------------------------------------------------------
+# TENO5-A cutoff (eq 2.16-2.18), the comparison scheme
+# --------------------------------------------------------------------------
+TENO5A = {"ndim": 1, "n": [8], "dx": [1.0], "bc": "periodic", "scheme": "teno5a"}
+
+
+def test_teno5a_cutoff_closed_forms(orc):
+    # Linear data: every sensor eta_j = (2 + eps)/(2 + eps) = 1, so m = 0,
+    # g = 1, beta = alpha_1 = 10.5 and C_T = 10^-10.
+    f, m, mask, tr = orc.rec([0.0, 1.0, 2.0, 3.0, 4.0], prob=TENO5A, trace=True)
+    assert (m, mask, tr["ct"], tr["x"], tr["theta"]) == (10, 7, 1e-10, 1.0, 10.5)
+    # A step (0,0,0,1,1): eta_i = eta_{i+1} = eps/(1 + eps), so m = 1 - 4 eps/(1+eps),
+    # g = O(eps^4), beta rounds to alpha_1 - alpha_2 = 7: C_T = 10^-7.
+    f, m, mask, tr = orc.rec([0.0, 0.0, 0.0, 1.0, 1.0], prob=TENO5A, trace=True)
+    assert (m, tr["ct"], tr["theta"]) == (7, 1e-7, 7.0)
+    # Differences (1, 1, 10, 10): eta_{i-1} = eta_{i+1} = 1 and
+    # eta_i = (20 + eps)/(101 + eps) = 0.19802..., m = 1 - eta_i/C_r = 0.20792...,
+    # g = (1 - m)^4 (1 + 4 m) = 0.7209..., beta = 10.5 - 3.5 (1 - g) = 9.523...:
+    # C_T = 10^-9.  (The printed denominator, which repeats df_{i+1/2}, would
+    # give eta_i = 0.1, beta = 7.30 and C_T = 10^-7.)
+    f, m, mask, tr = orc.rec([0.0, 1.0, 2.0, 12.0, 22.0], prob=TENO5A, trace=True)
+    assert m == 9 and tr["ct"] == 1e-9
+    assert abs(tr["x"] - 20.0 / 101.0) < 1e-6
+    assert abs(tr["theta"] - 9.5232) < 1e-3
+
+
+def test_teno5a_cutoff_range_and_symmetry(orc):
+    # The paper's range: C_T from 10^-7 (shocks) to 10^-10 (smooth), i.e.
+    # floor(beta) in [alpha_1 - alpha_2, alpha_1]; with the Rayleigh-Taylor
+    # parameters (alpha_2 = 5.5, C_r = 0.3) the range is [5, 10].  The
+    # sensor set {eta_{i-1}, eta_i, eta_{i+1}} is symmetric, so a reversed
+    # stencil gets the same cutoff.
+    rng = np.random.default_rng(21)
+    seen = set()
+    rt = dict(TENO5A, a2=5.5, cr=0.3)
+    seen_rt = set()
+    for _ in range(3000):
+        scale = 10.0 ** rng.uniform(-3, 3)
+        kind = rng.integers(3)
+        if kind == 0:
+            v = scale * rng.normal(size=5)
+        elif kind == 1:
+            v = scale * (np.arange(5) + 0.01 * rng.normal(size=5))
+        else:
+            v = scale * np.where(np.arange(5) < rng.integers(1, 5), 0.0, 1.0) + 1e-3 * rng.normal(size=5)
+        _, m, _ = orc.rec(v, prob=TENO5A)
+        assert 7 <= m <= 10
+        assert orc.rec(v[::-1].copy(), prob=TENO5A)[1] == m
+        seen.add(m)
+        _, mr, _ = orc.rec(v, prob=rt)
+        assert 5 <= mr <= 10
+        seen_rt.add(mr)
+    assert seen == {7, 8, 9, 10} and len(seen_rt) >= 5
