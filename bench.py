@@ -15,8 +15,9 @@ Beside the headline the same JSON line carries
                 around its launches inside the timed region;
   cpu_baseline  the FP64 oracle timed on the host cores on one RK3 step;
   schemes       2D four-quadrant Riemann problem at 2048^2 (eq 4.14 states),
-                TENO5-LAD against fixed-cutoff TENO5 and the linear upwind
-                scheme, next to the per-step times of Table 2;
+                TENO5-LAD against fixed-cutoff TENO5, TENO5-A (eq 2.16-2.18)
+                and the linear upwind scheme, next to the per-step times of
+                Table 2;
   batched       4096 ragged 1D shock tubes (N log-uniform in [128, 4096]),
                 500 steps of the persistent graph-replayed batch kernel
                 against teno_step per tube on the same GPU;
@@ -226,7 +227,7 @@ def schemes_leg(args, B, W, torch):
                                             "hardware": "desktop workstation CPU (Table 2)"}}
     reps = 20
     for name, kw in (("lad", {}), ("teno5_ct1e-5", {"scheme": "fixed_ct", "ct_fixed": 1e-5}),
-                     ("linear5", {"scheme": "linear5"})):
+                     ("teno5a", {"scheme": "teno5a"}), ("linear5", {"scheme": "linear5"})):
         prob = prob0.replace(**kw)
         S = B.Solver(prob)
         R = S.rhs(Ud0)
@@ -261,8 +262,11 @@ def schemes_leg(args, B, W, torch):
     out["lad_over_teno5_step"] = round(out["lad"]["ms_per_step"] / base["ms_per_step"], 4)
     out["lad_over_teno5_rhs"] = round(out["lad"]["rhs_ms"] / base["rhs_ms"], 4)
     out["linear5_over_teno5_rhs"] = round(out["linear5"]["rhs_ms"] / base["rhs_ms"], 4)
+    out["teno5a_over_teno5_step"] = round(out["teno5a"]["ms_per_step"] / base["ms_per_step"], 4)
+    out["teno5a_over_teno5_rhs"] = round(out["teno5a"]["rhs_ms"] / base["rhs_ms"], 4)
     print(f"[bench] schemes 2D: step LAD {out['lad']['ms_per_step']:.3f} ms, TENO5 "
-          f"{base['ms_per_step']:.3f} ms; rhs LAD {out['lad']['rhs_ms']:.3f}, TENO5 "
+          f"{base['ms_per_step']:.3f} ms, TENO5-A {out['teno5a']['ms_per_step']:.3f} ms; "
+          f"rhs LAD {out['lad']['rhs_ms']:.3f}, TENO5 "
           f"{base['rhs_ms']:.3f}, linear {out['linear5']['rhs_ms']:.3f} ms",
           file=sys.stderr, flush=True)
     return out

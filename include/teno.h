@@ -63,6 +63,10 @@ extern "C" {
 #define TENO_SCHEME_LAD 0
 #define TENO_SCHEME_FIXED_CT 1
 #define TENO_SCHEME_LINEAR5 2
+/* TENO5-A: the adaptive cutoff of Sec. 2 eq 2.16-2.18 (the paper's comparison
+ * scheme), C_T = 10^-floor(beta) from the sensor eta of the reconstruction's
+ * own five values. */
+#define TENO_SCHEME_TENO5A 3
 
 /* Grid, gas and scheme parameters (host struct, read at call time). */
 typedef struct teno_grid {
@@ -80,6 +84,10 @@ typedef struct teno_grid {
     double eps;        /* epsilon of eq 2.8 and eq 3.2 (paper: 1e-6)            */
     int32_t flags;     /* TENO_FLAG_* (0 for normal use)                        */
     int32_t reserved_;
+    double a1, a2;     /* TENO5-A alpha_1, alpha_2 of eq 2.16 (paper: 10.5, 3.5);
+                          0 <= a1 - a2, a1 <= 20                                */
+    double cr;         /* TENO5-A C_r of eq 2.17 (paper: 0.25); 0 < 0.9 cr < 1  */
+    double xi;         /* TENO5-A xi of eq 2.18 (paper: 1e-3); >= 0             */
 } teno_grid;
 
 /* teno_grid.flags: evaluate every cutoff decision with the literal formula

@@ -36,6 +36,10 @@ class TenoGrid(ctypes.Structure):
         ("eps", ctypes.c_double),
         ("flags", ctypes.c_int32),
         ("reserved_", ctypes.c_int32),
+        ("a1", ctypes.c_double),
+        ("a2", ctypes.c_double),
+        ("cr", ctypes.c_double),
+        ("xi", ctypes.c_double),
     ]
 
 
@@ -151,7 +155,7 @@ def _get(prob, key, default=None):
 
 def grid(prob) -> TenoGrid:
     """teno_grid from a problem description (attributes or dict keys ndim, n,
-    dx, bc, gamma, scheme, ct_fixed, H, Bl, Bu, eps)."""
+    dx, bc, gamma, scheme, ct_fixed, H, Bl, Bu, eps, a1, a2, cr, xi)."""
     g = TenoGrid()
     nd = int(_get(prob, "ndim"))
     n = list(_get(prob, "n"))
@@ -173,6 +177,10 @@ def grid(prob) -> TenoGrid:
     g.Bl = int(_get(prob, "Bl", 4))
     g.Bu = int(_get(prob, "Bu", 10))
     g.eps = float(_get(prob, "eps", 1e-6))
+    g.a1 = float(_get(prob, "a1", 10.5))
+    g.a2 = float(_get(prob, "a2", 3.5))
+    g.cr = float(_get(prob, "cr", 0.25))
+    g.xi = float(_get(prob, "xi", 1e-3))
     g.flags = ((FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0) |
                (FLAG_MASK_DIGEST if _get(prob, "mask_digest", False) else 0))
     return g

@@ -18,8 +18,12 @@ struct SchemeParams {
     double ct_fixed;
     double H;
     double eps;
-    int32_t scheme;  // 0 LAD, 1 fixed C_T, 2 linear (all stencils kept)
+    int32_t scheme;  // 0 LAD, 1 fixed C_T, 2 linear (all stencils kept), 3 TENO5-A
     int32_t Bl, Bu;
+    int32_t kA_nan;  // TENO5-A: exponent taken by a non-finite sensor, floor(a1 - a2)
+    double a1, a2;   // TENO5-A: alpha_1, alpha_2 of eq 2.16
+    double cr;       // TENO5-A: C_r of eq 2.17
+    double epsA;     // TENO5-A: 0.9 C_r / (1 - 0.9 C_r) xi^2 of eq 2.18 (host-evaluated)
 };
 
 // Ladder array of Sec. 3 eq 3.3 as decimal literals: kLadder[k] = 10^-k, so
@@ -167,8 +171,34 @@ constexpr double kDecisionMargin = 0x1p-40;
 
 // The literal decision of eq 2.8-2.14 / eq 3.1-3.4 (oracle operation order,
 // correctly rounded divisions).  Returns m | (mask << 5).
+// TENO5-A cutoff of eq 2.16-2.18 on the reconstruction's own values (a..e) =
+// (f_{i-2} .. f_{i+2}): sensors eta_j at j = i-1, i, i+1 (eq 2.18, denominator
+// df_{j+1/2}^2 + df_{j-1/2}^2), eta_{i+1/2} = their minimum, m = 1 - min(1,
+// eta / C_r), g = (1 - m)^4 (1 + 4 m), beta = alpha_1 - alpha_2 (1 - g),
+// C_T = 10^-floor(beta).  Operation order of the oracle; *k = floor(beta).
+__device__ __forceinline__ double teno5a_cutoff(const SchemeParams& S, double a, double b,
+                                                double c, double d, double e, int* k) {
+    const double df0 = b - a, df1 = c - b, df2 = d - c, df3 = e - d;
+    const double eta0 = cr_div(2.0 * fabs(df1 * df0) + S.epsA, (df1 * df1 + df0 * df0) + S.epsA);
+    const double eta1 = cr_div(2.0 * fabs(df2 * df1) + S.epsA, (df2 * df2 + df1 * df1) + S.epsA);
+    const double eta2 = cr_div(2.0 * fabs(df3 * df2) + S.epsA, (df3 * df3 + df2 * df2) + S.epsA);
+    double eh = eta0;
+    if (eta1 < eh) eh = eta1;
+    if (eta2 < eh) eh = eta2;
+    const double q = cr_div(eh, S.cr);
+    const double mA = 1.0 - (q < 1.0 ? q : 1.0);
+    const double om = 1.0 - mA;
+    const double om2 = om * om;
+    const double g = (om2 * om2) * (1.0 + 4.0 * mA);
+    const double bA = S.a1 - S.a2 * (1.0 - g);
+    const int kk = (bA >= 0.0) ? (int)floor(bA) : S.kA_nan;
+    *k = kk;
+    return kLadder[kk];
+}
+
 __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, double beta0,
-                                                      double beta1, double beta2) {
+                                                      double beta1, double beta2, double a,
+                                                      double b, double c, double d, double e) {
     const double tau = fabs(beta2 - beta0);
     const double t0 = cr_div(tau, beta0 + S.eps);
     const double t1 = cr_div(tau, beta1 + S.eps);
@@ -199,6 +229,8 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
         else
             m = S.Bl;
         ct = kLadder[m];
+    } else if (S.scheme == 3) {
+        ct = teno5a_cutoff(S, a, b, c, d, e, &m);
     } else {
         ct = S.ct_fixed;
     }
@@ -260,9 +292,16 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             const double g2 = (y2 * y2) * y2;
             const double sum = (g0 + g1) + g2;
             // chi_k = g_k / sum against the extreme cutoffs: a flag that is the
-            // same for every rung of the ladder needs no ladder index.
-            const double hi = K.ct_hi * (1.0 + kDecisionMargin) * sum;
-            const double lo = K.ct_lo * (1.0 - kDecisionMargin) * sum;
+            // same for every rung of the ladder needs no ladder index.  TENO5-A
+            // evaluates its cutoff exactly and uses it for both bounds.
+            double chi_hi = K.ct_hi, chi_lo = K.ct_lo;
+            if (S.scheme == 3) {
+                int kA;
+                chi_hi = chi_lo = teno5a_cutoff(S, a, b, c, d, e, &kA);
+                m = (uint32_t)kA;
+            }
+            const double hi = chi_hi * (1.0 + kDecisionMargin) * sum;
+            const double lo = chi_lo * (1.0 - kDecisionMargin) * sum;
             const bool k0 = g0 >= hi, k1 = g1 >= hi, k2 = g2 >= hi;
             const bool c0 = g0 < lo, c1 = g1 < lo, c2 = g2 < lo;
             sure = isfinite(sum) && (k0 || c0) && (k1 || c1) && (k2 || c2);
@@ -294,7 +333,7 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             }
         }
         cd = m | (mask << 5);
-        if (!sure) cd = teno5_decide_literal(S, beta0, beta1, beta2);
+        if (!sure) cd = teno5_decide_literal(S, beta0, beta1, beta2, a, b, c, d, e);
     }
     *code = cd;
     const uint32_t mask = cd >> 5;

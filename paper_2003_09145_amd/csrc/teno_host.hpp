@@ -26,9 +26,15 @@ inline int validate(const teno_grid* g) {
         }
     }
     if (!(g->gamma > 1.0)) return TENO_ERR_ARG;
-    if (g->scheme < 0 || g->scheme > 2) return TENO_ERR_ARG;
+    if (g->scheme < 0 || g->scheme > 3) return TENO_ERR_ARG;
     if (g->scheme == 0) {
         if (g->Bl < 0 || g->Bu > 20 || g->Bl > g->Bu || !(g->H > 0.0)) return TENO_ERR_ARG;
+    }
+    if (g->scheme == 3) {
+        // floor(beta) of eq 2.16 stays in [floor(a1 - a2), floor(a1)] within the ladder
+        if (!(g->a2 >= 0.0) || !(g->a1 - g->a2 >= 0.0) || !(g->a1 <= 20.0)) return TENO_ERR_ARG;
+        if (!(g->cr > 0.0) || !(0.9 * g->cr < 1.0) || !(g->xi >= 0.0) || !std::isfinite(g->xi))
+            return TENO_ERR_ARG;
     }
     if (!(g->eps > 0.0)) return TENO_ERR_ARG;
     if (g->flags & ~(TENO_FLAG_LITERAL_DECISIONS | TENO_FLAG_MASK_DIGEST)) return TENO_ERR_ARG;
@@ -44,6 +50,15 @@ inline SchemeParams scheme_of(const teno_grid* g) {
     s.scheme = g->scheme;
     s.Bl = g->Bl;
     s.Bu = g->Bu;
+    s.a1 = g->a1;
+    s.a2 = g->a2;
+    s.cr = g->cr;
+    s.kA_nan = 0;
+    s.epsA = 0.0;
+    if (g->scheme == 3) {
+        s.kA_nan = (int)std::floor(g->a1 - g->a2);
+        s.epsA = ((0.9 * g->cr) / (1.0 - 0.9 * g->cr)) * (g->xi * g->xi);  // eq 2.18
+    }
     return s;
 }
 
@@ -86,6 +101,15 @@ inline DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
     K.smooth_t = -1.0;
     if (g->scheme == TENO_SCHEME_FIXED_CT) {
         K.ct_hi = K.ct_lo = g->ct_fixed;
+        K.smooth_t = smooth_bound(K.ct_hi);
+        return K;
+    }
+    if (g->scheme == TENO_SCHEME_TENO5A) {
+        // the cutoff is evaluated per reconstruction; its largest value bounds
+        // the smooth-stencil shortcut
+        const int khi = (int)std::floor(g->a1 - g->a2);
+        K.ct_hi = kLadderHost[khi];
+        K.ct_lo = kLadderHost[20];
         K.smooth_t = smooth_bound(K.ct_hi);
         return K;
     }

@@ -49,9 +49,10 @@ def test_struct_layout_matches_header(tmp_path, B):
 #include <stddef.h>
 #include "teno.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(teno_grid), offsetof(teno_grid, dx),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(teno_grid), offsetof(teno_grid, dx),
          offsetof(teno_grid, bc), offsetof(teno_grid, gamma), offsetof(teno_grid, H),
-         offsetof(teno_grid, Bl), offsetof(teno_grid, eps), offsetof(teno_grid, flags));
+         offsetof(teno_grid, Bl), offsetof(teno_grid, eps), offsetof(teno_grid, flags),
+         offsetof(teno_grid, a1), offsetof(teno_grid, xi));
   printf("%zu %zu %zu %zu %zu\n", sizeof(teno_ctrl), offsetof(teno_ctrl, alpha),
          offsetof(teno_ctrl, status), offsetof(teno_ctrl, nsteps), offsetof(teno_ctrl, active));
   return 0;
@@ -63,7 +64,7 @@ int main(void) {
     G, C = B.TenoGrid, B.TenoCtrl
     assert [int(x) for x in out[0].split()] == [
         ctypes.sizeof(G), G.dx.offset, G.bc.offset, G.gamma.offset, G.H.offset, G.Bl.offset,
-        G.eps.offset, G.flags.offset]
+        G.eps.offset, G.flags.offset, G.a1.offset, G.xi.offset]
     assert [int(x) for x in out[1].split()] == [
         ctypes.sizeof(C), C.alpha.offset, C.status.offset, C.nsteps.offset, C.active.offset]
 
@@ -85,7 +86,10 @@ def test_workspace_bytes(B):
 @pytest.mark.parametrize("kw", [
     dict(ndim=0), dict(ndim=4, n=[8, 8, 8, 8]), dict(n=[2, 12]), dict(dx=[0.0, 0.1]),
     dict(dx=[0.1, -1.0]), dict(bc=[7, 0]), dict(gamma=1.0), dict(scheme=5),
-    dict(Bl=5, Bu=4), dict(Bu=21), dict(H=0.0), dict(eps=0.0)])
+    dict(Bl=5, Bu=4), dict(Bu=21), dict(H=0.0), dict(eps=0.0),
+    dict(scheme="teno5a", a1=3.0, a2=3.5), dict(scheme="teno5a", a1=21.0),
+    dict(scheme="teno5a", cr=0.0), dict(scheme="teno5a", cr=1.2), dict(scheme="teno5a", xi=-1.0),
+    dict(scheme="teno5a", a2=-1.0)])
 def test_validation_rejects_bad_grids(B, kw):
     try:
         g = _grid(B, **kw)

@@ -50,6 +50,9 @@ SMALL = {
     "3d_mixed": lambda: (lambda p: (p, W.random_field(p, seed=24)))(
         W.uniform_problem(3, [5, 5, 4], [0.0] * 3, [1.0] * 3,
                           ["transmissive", "periodic", "reflective"])),
+    "2d_teno5a": lambda: (lambda p: (p, W.random_field(p, seed=25)))(
+        W.uniform_problem(2, [7, 6], [0.0, 0.0], [1.0, 1.0], ["periodic", "transmissive"],
+                          scheme="teno5a")),
 }
 
 

@@ -161,3 +161,23 @@ def test_batch_full_config_sampled(torch, B, orc):
         Uc, tc = _tube_oracle(orc, batch, b, steps)
         assert np.array_equal(Ug[:, batch.offsets[b]:batch.offsets[b + 1]], Uc), b
         assert t[b] == tc
+
+
+def test_batch_teno5a_matches_oracle(torch, B, orc):
+    # the TENO5-A cutoff (eq 2.16-2.18) through the batched kernel
+    batch = small_batch(seed=13, count=16)
+    steps = 5
+    P = B.BatchPlan(batch.lengths, batch.dx, prob={"scheme": "teno5a"})
+    Ud = torch.from_numpy(batch.U.copy()).cuda()
+    P.init(Ud)
+    for _ in range(steps):
+        P.step(Ud)
+    torch.cuda.synchronize()
+    Ug = Ud.cpu().numpy()
+    for b in range(batch.nbatch):
+        prob = batch.tube_problem(b, scheme="teno5a")
+        U = batch.tube(b).copy()
+        t = 0.0
+        for _ in range(steps):
+            U, t, dt, a9, st = orc.step(prob, U, 0.5, t, np.inf)
+        assert np.array_equal(Ug[:, batch.offsets[b]:batch.offsets[b + 1]], U[:, 0, 0, :]), b

@@ -104,7 +104,7 @@ def test_rhs_parity_literal_decisions(torch, B, orc, name):
     assert np.array_equal(Rf, Rl) and np.array_equal(df, dl)
 
 
-@pytest.mark.parametrize("scheme", ["fixed_ct", "linear5"])
+@pytest.mark.parametrize("scheme", ["fixed_ct", "linear5", "teno5a"])
 def test_rhs_parity_other_schemes(torch, B, orc, scheme):
     prob = W.uniform_problem(2, [40, 33], [0.0, 0.0], [1.0, 1.0], "transmissive",
                              scheme=scheme, ct_fixed=1e-6)
@@ -113,6 +113,35 @@ def test_rhs_parity_other_schemes(torch, B, orc, scheme):
     Rc, dc = orc.rhs(prob, U, dump=True)
     flips, rel, bitwise = compare(Rg, Rc, dg, dc, scheme)
     assert flips == 0 and rel <= REL and bitwise
+
+
+# TENO5-A (eq 2.16-2.18): RHS with every decision (cutoff exponent and
+# mask), the literal-decision mode, and steps (no decision dump, so the
+# smooth-stencil shortcut is on), with the default and the Rayleigh-Taylor
+# parameter sets.
+@pytest.mark.parametrize("name,kw,steps", [
+    ("1d_shu_osher400", {}, 6), ("2d_riemann3_96x80", {}, 3),
+    ("3d_random21x18x13_mixed", {}, 2), ("1d_blast400_reflective", {"a2": 5.5, "cr": 0.3}, 4),
+    ("3d_turbulence24", {"a2": 5.5, "cr": 0.3}, 2)])
+def test_teno5a_parity(torch, B, orc, name, kw, steps):
+    prob, U = CASES[name]()
+    prob = prob.replace(scheme="teno5a", **kw)
+    Rg, dg, _, _ = _gpu_rhs(torch, B, prob, U)
+    Rc, dc = orc.rhs(prob, U, dump=True)
+    flips, rel, bitwise = compare(Rg, Rc, dg, dc, name + " teno5a")
+    assert flips == 0 and bitwise
+    assert set(np.unique(dc & 31)) <= set(range(int(np.floor(prob.a1 - prob.a2)), 11))
+    lit = prob.replace()
+    lit.literal_decisions = True
+    Rl, dl, _, _ = _gpu_rhs(torch, B, lit, U)
+    assert np.array_equal(Rl, Rg) and np.array_equal(dl, dg)
+    Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
+    Uc = U.copy()
+    t = 0.0
+    for _ in range(steps):
+        Uc, t, dt, a9, st = orc.step(prob, Uc, 0.5, t, 1e9)
+    assert c.status == st
+    assert np.array_equal(Ug, Uc)
 
 
 def test_rhs_frozen_alpha(torch, B, orc):
