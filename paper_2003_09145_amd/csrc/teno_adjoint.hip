@@ -44,7 +44,7 @@ __device__ __forceinline__ double cand_coef(const double* w, int m) {
     }
 }
 
-template <int ND, int DIR>
+template <int ND, int DIR, bool A5>
 __device__ __forceinline__ void face_adjoint(const double (&q)[6][ND + 2], double alpha,
                                              double gm1, const SchemeParams& S,
                                              const DecisionConsts& K,
@@ -161,7 +161,7 @@ __device__ __forceinline__ void face_adjoint(const double (&q)[6][ND + 2], doubl
                 v[m] = acc;
             }
             uint32_t code;
-            rsg[sg] = teno5_rec_fast(S, K, omega, v[0], v[1], v[2], v[3], v[4], &code);
+            rsg[sg] = teno5_rec_fast<A5>(S, K, omega, v[0], v[1], v[2], v[3], v[4], &code);
             mask[s][sg] = code >> 5;
         }
         fh[s] = rsg[0] + rsg[1];
@@ -348,7 +348,7 @@ struct AdjArgs {
     DecisionConsts dk;
 };
 
-template <int ND, int DIR>
+template <int ND, int DIR, bool A5>
 __global__ __launch_bounds__(64) void k_adj_faces(AdjArgs A) {
     constexpr int NC = ND + 2;
     __shared__ double omega[24];
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(64) void k_adj_faces(AdjArgs A) {
         mu[c] = (lr - ll) / A.dx;
     }
     double gq[6][NC];
-    face_adjoint<ND, DIR>(q, A.alpha[DIR], A.sch.gamma - 1.0, A.sch, A.dk, omega, mu, gq);
+    face_adjoint<ND, DIR, A5>(q, A.alpha[DIR], A.sch.gamma - 1.0, A.sch, A.dk, omega, mu, gq);
     double* Gp = A.G + id * 6 * NC;
 #pragma unroll
     for (int m = 0; m < 6; ++m)
@@ -494,7 +494,12 @@ static size_t adj_ws_bytes(const teno_grid* g) {
 template <int ND, int DIR>
 static hipError_t launch_adj(AdjArgs A, hipStream_t st) {
     const int64_t nf = A.ncols * A.ftot;
-    hipLaunchKernelGGL((k_adj_faces<ND, DIR>), dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, st, A);
+    if (A.sch.scheme == TENO_SCHEME_TENO5A)
+        hipLaunchKernelGGL((k_adj_faces<ND, DIR, true>), dim3((unsigned)((nf + 63) / 64)), dim3(64), 0,
+                           st, A);
+    else
+        hipLaunchKernelGGL((k_adj_faces<ND, DIR, false>), dim3((unsigned)((nf + 63) / 64)), dim3(64),
+                           0, st, A);
     hipLaunchKernelGGL((k_adj_cells<ND, DIR>), dim3((unsigned)((A.ncell + 255) / 256)), dim3(256), 0, st,
                        A);
     return hipGetLastError();

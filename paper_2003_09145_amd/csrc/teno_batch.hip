@@ -99,7 +99,7 @@ __device__ __forceinline__ void tube_max(bool active, int tube, double v,
     }
 }
 
-template <int W>
+template <int W, bool A5>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_stage(
     BatchArgs A) {
     constexpr int ND = 1, DIR = 0, NC = 3, NV = 2 * NC + ND + 2;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (valid) {
             const int o = (int)(F + 5 * (int64_t)b - e_lo);
             double Fh[NC];
-            face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, nullptr, Fh);
+            face_flux<ND, DIR, A5>(ext, cap, o, gm1, A.sch, A.dk, omega, nullptr, Fh);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
         }
@@ -343,10 +343,14 @@ hipError_t launch_stage(teno_batch_plan* P, double* U, int stage, int W, int bpc
     A.dk = decision_consts(&P->g, false);
     const int64_t grid = grid_for(P, W, bpc);
     const size_t lds = lds_bytes(P, W);
-    switch (W) {
-        case 1: hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(64), lds, st, A); break;
-        case 2: hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(128), lds, st, A); break;
-        default: hipLaunchKernelGGL(k_batch_stage<4>, dim3((unsigned)grid), dim3(256), lds, st, A); break;
+    const bool a5 = P->g.scheme == TENO_SCHEME_TENO5A;
+    switch (W + (a5 ? 8 : 0)) {
+        case 1: hipLaunchKernelGGL((k_batch_stage<1, false>), dim3((unsigned)grid), dim3(64), lds, st, A); break;
+        case 2: hipLaunchKernelGGL((k_batch_stage<2, false>), dim3((unsigned)grid), dim3(128), lds, st, A); break;
+        case 4: hipLaunchKernelGGL((k_batch_stage<4, false>), dim3((unsigned)grid), dim3(256), lds, st, A); break;
+        case 9: hipLaunchKernelGGL((k_batch_stage<1, true>), dim3((unsigned)grid), dim3(64), lds, st, A); break;
+        case 10: hipLaunchKernelGGL((k_batch_stage<2, true>), dim3((unsigned)grid), dim3(128), lds, st, A); break;
+        default: hipLaunchKernelGGL((k_batch_stage<4, true>), dim3((unsigned)grid), dim3(256), lds, st, A); break;
     }
     return hipGetLastError();
 }
@@ -458,7 +462,9 @@ int teno_batch_plan_create(const teno_grid* g, int64_t nbatch, const int64_t* le
     P->waves = (lds_bytes(P, 4) <= 64 * 1024) ? 4 : 1;
     int occ = 0;
     if (P->waves == 4 &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_stage<4>, 256, lds_bytes(P, 4)) ==
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, (g->scheme == TENO_SCHEME_TENO5A) ? k_batch_stage<4, true> : k_batch_stage<4, false>,
+            256, lds_bytes(P, 4)) ==
             hipSuccess && occ > 0)
         P->blocks_per_cu = occ;
     const size_t nb = (size_t)nbatch;

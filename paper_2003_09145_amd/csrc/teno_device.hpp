@@ -196,6 +196,9 @@ __device__ __forceinline__ double teno5a_cutoff(const SchemeParams& S, double a,
     return kLadder[kk];
 }
 
+// A5: the launch runs TENO5-A (scheme 3); its cutoff code is compiled only
+// into the A5 instantiations, so the other schemes' kernels do not carry it.
+template <bool A5>
 __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, double beta0,
                                                       double beta1, double beta2, double a,
                                                       double b, double c, double d, double e) {
@@ -229,7 +232,7 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
         else
             m = S.Bl;
         ct = kLadder[m];
-    } else if (S.scheme == 3) {
+    } else if (A5) {
         ct = teno5a_cutoff(S, a, b, c, d, e, &m);
     } else {
         ct = S.ct_fixed;
@@ -250,6 +253,7 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
 // equal the literal ones exactly.  The flux itself is the literal
 // combination with the eq 2.15 weights of the chosen mask.
 // *code receives m | (mask << 5).
+template <bool A5>
 __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const DecisionConsts& K,
                                                  const double* __restrict__ omega_lds,
                                                  double a, double b, double c, double d,
@@ -295,7 +299,7 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             // same for every rung of the ladder needs no ladder index.  TENO5-A
             // evaluates its cutoff exactly and uses it for both bounds.
             double chi_hi = K.ct_hi, chi_lo = K.ct_lo;
-            if (S.scheme == 3) {
+            if (A5) {
                 int kA;
                 chi_hi = chi_lo = teno5a_cutoff(S, a, b, c, d, e, &kA);
                 m = (uint32_t)kA;
@@ -333,7 +337,7 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             }
         }
         cd = m | (mask << 5);
-        if (!sure) cd = teno5_decide_literal(S, beta0, beta1, beta2, a, b, c, d, e);
+        if (!sure) cd = teno5_decide_literal<A5>(S, beta0, beta1, beta2, a, b, c, d, e);
     }
     *code = cd;
     const uint32_t mask = cd >> 5;

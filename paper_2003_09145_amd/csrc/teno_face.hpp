@@ -58,10 +58,11 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
 // Numerical flux at the face between stencil cells o + 2 and o + 3 (cells
 // i-2 .. i+3 at o .. o + 5): Roe average, left/right eigenvectors, projection
 // of the split fluxes, TENO5-LAD reconstruction of f+ and f- per
-// characteristic field, back-projection.  Fnat receives the flux in natural
+// characteristic field, back-projection (A5: TENO5-A cutoff, scheme 3).
+// Fnat receives the flux in natural
 // component order; o8 (nullable) receives the 2 NC decision codes and masks
 // (nullable, initialised by the caller) the 2 NC cutoff masks, 3 bits each.
-template <int ND, int DIR>
+template <int ND, int DIR, bool A5>
 __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int cap, int o,
                                       double gm1, const SchemeParams& sch,
                                       const DecisionConsts& dk,
@@ -156,7 +157,7 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
                 v[j] = acc;
             }
             uint32_t code;
-            const double r = teno5_rec_fast(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
+            const double r = teno5_rec_fast<A5>(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
             if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
             if (masks != nullptr) *masks |= (code >> 5) << (3 * (2 * s + sg));
             fh = sg ? fh + r : r;

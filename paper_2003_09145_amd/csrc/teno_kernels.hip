@@ -80,7 +80,7 @@ __device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
 // CAPC: the stencil-buffer stride when it is known at compile time (it is
 // ext_cap_for(n) = 74 for every n >= 63), so that every LDS stencil read is a
 // per-lane base plus an immediate offset; 0: taken from A.ext_cap.
-template <int ND, int DIR, int W, bool DIGEST, int CAPC>
+template <int ND, int DIR, int W, bool DIGEST, int CAPC, bool A5>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
@@ -136,19 +136,29 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double gm1 = A.sch.gamma - 1.0;
     const int64_t be0 = e_lo / np6;                 // line of the first ext cell (uniform)
     const int je0 = (int)(e_lo - be0 * np6);
-    for (int idx = lane; idx < count; idx += 64) {
+    // COOP (y and z sweeps, 4 waves = 4 neighbouring columns of one line chunk,
+    // which the host guarantees): thread t stages column t % 4, so a wave's
+    // loads cover 16 cells x 4 neighbouring x (16 cache lines, not 64).
+    constexpr bool COOP = (CAPC != 0) && (DIR != 0) && (W == 4);
+    const int64_t col0 = col - wave;  // first column of the block (uniform)
+    {
+    const int cc = COOP ? (int)(threadIdx.x & 3) : wave;  // column slot within the block
+    const int64_t colbase_c = (col0 + cc) * A.col_step;
+    double* ext_c = smem + 24 + (size_t)cc * per_wave;
+    for (int idx = COOP ? (int)(threadIdx.x >> 2) : lane; idx < count; idx += 64) {
         const int jq = je0 + idx;
         const int bw = jq / (int)np6;
         const int64_t b = be0 + bw;
         const int j = jq - bw * (int)np6 - 3;
         bool flip;
         const int src = ghost_src(A.bc, n, j, &flip);
-        const int64_t cell = colbase + b * A.line_step + (int64_t)src * A.stride;
+        const int64_t cell = colbase_c + b * A.line_step + (int64_t)src * A.stride;
         double q[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
         if (flip) q[1 + DIR] = -q[1 + DIR];
-        stage_cell<ND, DIR>(q, alpha, gm1, ext, cap, idx);
+        stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, idx);
+    }
     }
     __syncthreads();
 
@@ -168,7 +178,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         double Fh[NC];
         uint32_t masks = 0;
-        face_flux<ND, DIR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
+        face_flux<ND, DIR, A5>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
                            want_digest ? &masks : nullptr);
 #pragma unroll
         for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
@@ -191,13 +201,31 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     __syncthreads();
 
     // ---- flux difference and epilogue ---------------------------------------
-    if (valid && lane > 0 && phi > 0) {
+    // Face j of the chunk (j >= 1) updates its left cell from the fluxes at
+    // faces j and j - 1 (COOP: thread t updates column t % 4, face t / 4).
+    int jj = lane;
+    int64_t blj = bl, phij = phi;
+    bool upd = valid && lane > 0 && phi > 0;
+    const double* fh_c = fhs;
+    int64_t colbase_j = (DIR == 0) ? 0 : colbase;
+    if constexpr (COOP) {
+        jj = (int)(threadIdx.x >> 2);
+        const int tqj = phi0 + jj;
+        const int wrj = tqj / (int)np1;
+        blj = bl0 + wrj;
+        phij = tqj - wrj * (int)np1;
+        upd = F0 + jj < A.ftot && jj > 0 && phij > 0;
+        const int cc = (int)(threadIdx.x & 3);
+        fh_c = smem + 24 + (size_t)cc * per_wave;
+        colbase_j = (col0 + cc) * A.col_step;
+    }
+    if (upd) {
         const double rdx = rcp_nr(A.dx);
-        const int64_t cell = colbase + bl * A.line_step + (phi - 1) * A.stride;
+        const int64_t cell = colbase_j + blj * A.line_step + (phij - 1) * A.stride;
         double r[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double diff = fhs[c * 64 + lane] - fhs[c * 64 + lane - 1];
+            const double diff = fh_c[c * 64 + jj] - fh_c[c * 64 + jj - 1];
             const double prev = (A.Rin != nullptr) ? A.Rin[c * A.ncell + cell] : 0.0;
             r[c] = prev - cr_div_r(diff, A.dx, rdx);
         }
@@ -458,7 +486,7 @@ static Scratch* scratch_of(const teno_grid* g, void* ws) {
     return (Scratch*)((char*)ws + 3 * state_bytes(g));
 }
 
-template <int ND, int DIR>
+template <int ND, int DIR, bool A5>
 static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;
@@ -466,24 +494,26 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     const size_t per_wave =
         (size_t)((A.ext_cap * NV > 64 * NC) ? A.ext_cap * NV : 64 * NC) * sizeof(double);
     const size_t table = 24 * sizeof(double);
-    if (!digest && A.ext_cap == kCapLong) {
+    // the fixed-stride variant; along y and z it stages and updates four
+    // neighbouring columns per block, which needs whole blocks of columns
+    if (!digest && A.ext_cap == kCapLong && (DIR == 0 || A.ncols % 4 == 0)) {
         const int64_t blocks = (A.nchunks + 3) / 4;
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong, A5>), dim3((unsigned)blocks),
                            dim3(256), table + 4 * per_wave, st, A);
     } else if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
         const int64_t blocks = (A.nchunks + 3) / 4;
         if (digest)
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true, 0>), dim3((unsigned)blocks), dim3(256),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true, 0, A5>), dim3((unsigned)blocks), dim3(256),
                                table + 4 * per_wave, st, A);
         else
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, 0>), dim3((unsigned)blocks), dim3(256),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, 0, A5>), dim3((unsigned)blocks), dim3(256),
                                table + 4 * per_wave, st, A);
     } else {
         if (digest)
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, true, 0>), dim3((unsigned)A.nchunks), dim3(64),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, true, 0, A5>), dim3((unsigned)A.nchunks), dim3(64),
                                table + per_wave, st, A);
         else
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, 0>), dim3((unsigned)A.nchunks), dim3(64),
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, 0, A5>), dim3((unsigned)A.nchunks), dim3(64),
                                table + per_wave, st, A);
     }
     return hipGetLastError();
@@ -523,13 +553,20 @@ static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStre
     const int64_t chunks_per_col = (A.ftot - 1 + kCellsPerChunk - 1) / kCellsPerChunk;
     A.nchunks = chunks_per_col * A.ncols;
     const bool digest = A.digest != nullptr && (g->flags & TENO_FLAG_MASK_DIGEST) != 0;
-    switch (g->ndim * 4 + dir) {
-        case 4: return launch_sweep_t<1, 0>(A, digest, st);
-        case 8: return launch_sweep_t<2, 0>(A, digest, st);
-        case 9: return launch_sweep_t<2, 1>(A, digest, st);
-        case 12: return launch_sweep_t<3, 0>(A, digest, st);
-        case 13: return launch_sweep_t<3, 1>(A, digest, st);
-        case 14: return launch_sweep_t<3, 2>(A, digest, st);
+    const int key = g->ndim * 4 + dir + (g->scheme == TENO_SCHEME_TENO5A ? 16 : 0);
+    switch (key) {
+        case 4: return launch_sweep_t<1, 0, false>(A, digest, st);
+        case 8: return launch_sweep_t<2, 0, false>(A, digest, st);
+        case 9: return launch_sweep_t<2, 1, false>(A, digest, st);
+        case 12: return launch_sweep_t<3, 0, false>(A, digest, st);
+        case 13: return launch_sweep_t<3, 1, false>(A, digest, st);
+        case 14: return launch_sweep_t<3, 2, false>(A, digest, st);
+        case 20: return launch_sweep_t<1, 0, true>(A, digest, st);
+        case 24: return launch_sweep_t<2, 0, true>(A, digest, st);
+        case 25: return launch_sweep_t<2, 1, true>(A, digest, st);
+        case 28: return launch_sweep_t<3, 0, true>(A, digest, st);
+        case 29: return launch_sweep_t<3, 1, true>(A, digest, st);
+        case 30: return launch_sweep_t<3, 2, true>(A, digest, st);
     }
     return hipErrorInvalidValue;
 }

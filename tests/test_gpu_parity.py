@@ -72,6 +72,14 @@ CASES = {
     "3d_turbulence24": lambda: W.turbulence_3d(24),
     "3d_random9x8x7_periodic": lambda: (lambda p: (p, W.random_field(p, seed=9)))(
         W.uniform_problem(3, [9, 8, 7], [0.0] * 3, [1.0] * 3, "periodic")),
+    # every axis >= 63 cells (the fixed-stride sweeps; y and z with four
+    # columns per block since nx % 4 == 0), ragged chunk tails on each axis
+    "3d_random64x65x70_mixed": lambda: (lambda p: (p, W.random_field(p, seed=10)))(
+        W.uniform_problem(3, [64, 65, 70], [0.0] * 3, [1.0] * 3,
+                          ["periodic", "reflective", "transmissive"])),
+    # nx % 4 != 0: the y sweep falls back to one column per wave
+    "2d_random98x70_mixed": lambda: (lambda p: (p, W.random_field(p, seed=11)))(
+        W.uniform_problem(2, [98, 70], [0.0, 0.0], [1.0, 1.0], ["transmissive", "periodic"])),
 }
 
 
@@ -182,7 +190,8 @@ def _gpu_steps(torch, B, prob, U, cfl, t_end, nsteps):
 
 
 @pytest.mark.parametrize("name,steps", [("1d_sod200", 12), ("2d_riemann3_96x80", 4),
-                                        ("3d_random21x18x13_mixed", 3), ("3d_turbulence24", 3)])
+                                        ("3d_random21x18x13_mixed", 3), ("3d_turbulence24", 3),
+                                        ("3d_random64x65x70_mixed", 2)])
 def test_step_parity(torch, B, orc, name, steps):
     prob, U = CASES[name]()
     Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
