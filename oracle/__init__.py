@@ -48,6 +48,13 @@ class OrParams(ctypes.Structure):
         ("a2", ctypes.c_double),
         ("cr", ctypes.c_double),
         ("xi", ctypes.c_double),
+        ("has_ext", ctypes.c_int32),
+        ("side_kind", ctypes.c_int32 * 12),
+        ("side_axis", ctypes.c_int32 * 6),
+        ("side_split", ctypes.c_double * 12),
+        ("side_state", ctypes.c_double * 60),
+        ("gravity", ctypes.c_double * 3),
+        ("time", ctypes.c_double),
     ]
 
 
@@ -133,6 +140,27 @@ def params(prob) -> OrParams:
     p.a2 = float(_get(prob, "a2", 3.5))
     p.cr = float(_get(prob, "cr", 0.25))
     p.xi = float(_get(prob, "xi", 1e-3))
+    bnd = _get(prob, "boundary", None)
+    if bnd is not None:
+        kinds = dict(BC, fixed=3)
+        p.has_ext = 1
+        for d in range(3):
+            for e in range(2):
+                sd = bnd.sides[d][e]
+                ka = kinds[sd.kind_a]
+                kb = kinds[sd.kind_b] if sd.kind_b is not None else ka
+                p.side_kind[(d * 2 + e) * 2 + 0] = ka
+                p.side_kind[(d * 2 + e) * 2 + 1] = kb
+                p.side_axis[d * 2 + e] = int(sd.split_axis)
+                p.side_split[(d * 2 + e) * 2 + 0] = float(sd.split0)
+                p.side_split[(d * 2 + e) * 2 + 1] = float(sd.split_rate)
+                for w, st in enumerate((sd.state_a, sd.state_b)):
+                    if st is not None:
+                        for q, v in enumerate(st):
+                            p.side_state[((d * 2 + e) * 2 + w) * 5 + q] = float(v)
+        for k in range(3):
+            p.gravity[k] = float(bnd.gravity[k])
+        p.time = float(bnd.time)
     return p
 
 

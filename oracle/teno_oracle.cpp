@@ -30,7 +30,12 @@
  *  - the chi-tilde of the LAD function and gamma_k share one epsilon;
  *  - 3D time step: dt = sigma / (a_x/dx + a_y/dy + a_z/dz);
  *  - ghost cells: periodic wrap, zero-gradient copy, or mirror with the
- *    normal momentum negated (reflecting wall), 3 per side.
+ *    normal momentum negated (reflecting wall), 3 per side; with per-side
+ *    boundaries also a fixed state, chosen along the boundary by a split
+ *    that may move in time (evaluated at the stage times t, t + dt,
+ *    t + dt/2);
+ *  - the gravity source of the Rayleigh-Taylor problem is added after the
+ *    flux differences.
  */
 #include <cmath>
 #include <cstdint>
@@ -54,6 +59,16 @@ typedef struct {
     double eps;         /* epsilon of eq 2.8 / eq 3.2                       */
     double a1, a2;      /* TENO5-A: alpha_1, alpha_2 of eq 2.16             */
     double cr, xi;      /* TENO5-A: C_r of eq 2.17, xi of eq 2.18           */
+    /* Boundaries that differ per end, along the boundary or in time, and a
+     * gravity source (the 2D workloads of Sec. 4.3).  Used when has_ext. */
+    int32_t has_ext;
+    int32_t side_kind[3][2][2];    /* [axis][end][a, b]: 0 periodic, 1 zero-gradient,
+                                      2 reflecting, 3 fixed state                     */
+    int32_t side_axis[3][2];       /* axis of the split coordinate, -1: kind a only  */
+    double side_split[3][2][2];    /* split position = split0 + rate * t           */
+    double side_state[3][2][2][5]; /* conserved fixed states (natural order)        */
+    double gravity[3];             /* momentum += rho g, energy += m . g            */
+    double time;                   /* time of or_rhs evaluations                    */
 } OrParams;
 
 }  // extern "C"
@@ -411,14 +426,34 @@ inline int ghost_source(int bc, int n, int j, bool* flip) {
     return j < 0 ? -1 - j : 2 * n - 1 - j;
 }
 
-/* Load the conserved state of line cell j (natural order) into out[]. */
+/* Load the conserved state of line cell j (natural order) into out[] at time
+ * t.  With per-side boundaries, a ghost cell takes the kind of its end: kind
+ * a where the split coordinate (the cell centre (i + 1/2) dx along the split
+ * axis, on the line) lies below split0 + rate t, else kind b; a fixed kind
+ * supplies its stored state. */
 template <class T>
 void load_cell(const OrParams& P, const T* U, int d, const int base[3], int j,
-               T* out) {
+               T* out, double t) {
     int nc = P.ndim + 2;
     int64_t N = ncells(P);
     bool flip;
-    int src = ghost_source(P.bc[d], P.n[d], j, &flip);
+    int kind = P.bc[d];
+    if (P.has_ext && (j < 0 || j >= P.n[d])) {
+        int end = j < 0 ? 0 : 1;
+        int ax = P.side_axis[d][end];
+        int which = 0;  /* 0: kind a, 1: kind b */
+        if (ax >= 0) {
+            double coord = ((double)base[ax] + 0.5) * P.dx[ax];
+            double split = P.side_split[d][end][0] + P.side_split[d][end][1] * t;
+            if (!(coord < split)) which = 1;
+        }
+        kind = P.side_kind[d][end][which];
+        if (kind == 3) {
+            for (int q = 0; q < nc; ++q) out[q] = from_double<T>(P.side_state[d][end][which][q]);
+            return;
+        }
+    }
+    int src = ghost_source(kind, P.n[d], j, &flip);
     int pos[3] = {base[0], base[1], base[2]};
     pos[d] = src;
     int64_t ci = cell_index(P, pos[0], pos[1], pos[2]);
@@ -530,7 +565,7 @@ void lf_alpha(const OrParams& P, const double* U, double alpha[3], int* status) 
 /* ------------------------------------------------------------------------ */
 template <class T>
 void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
-              uint8_t* dump) {
+              uint8_t* dump, double t) {
     int nd = P.ndim, nc = nd + 2;
     int64_t N = ncells(P);
     for (int64_t i = 0; i < (int64_t)nc * N; ++i) out[i] = from_double<T>(0.0);
@@ -546,7 +581,7 @@ void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
             /* The line with 3 ghost cells per side. */
             std::vector<T> ext((size_t)(n + 6) * 5);
             for (int j = -3; j < n + 3; ++j)
-                load_cell(P, U, d, base, j, &ext[(size_t)(j + 3) * 5]);
+                load_cell(P, U, d, base, j, &ext[(size_t)(j + 3) * 5], t);
             std::vector<T> fl((size_t)(n + 1) * 5);
             for (int phi = 0; phi <= n; ++phi) {  /* face i+1/2, i = phi-1 */
                 T st[6][5];
@@ -570,6 +605,17 @@ void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
             }
         }
         dump_off += L * (int64_t)(n + 1) * 2 * nc;
+    }
+    /* Gravity source (Sec. 4.3, Rayleigh-Taylor): rho g_d on each momentum
+     * component, m . g on the energy, added after the flux differences. */
+    if (P.has_ext) {
+        for (int64_t i = 0; i < N; ++i) {
+            for (int dd = 0; dd < nd; ++dd)
+                out[(1 + dd) * N + i] = out[(1 + dd) * N + i] + U[i] * P.gravity[dd];
+            T sE = U[1 * N + i] * P.gravity[0];
+            for (int dd = 1; dd < nd; ++dd) sE = sE + U[(1 + dd) * N + i] * P.gravity[dd];
+            out[(nc - 1) * N + i] = out[(nc - 1) * N + i] + sE;
+        }
     }
 }
 
@@ -595,7 +641,7 @@ void rhs_cells_impl(const OrParams& P, const double* U, const double alpha[3],
             for (int side = 0; side < 2; ++side) {
                 int phi = i + side;  /* face i-1/2 (phi = i) and i+1/2 */
                 double st[6][5];
-                for (int j = 0; j < 6; ++j) load_cell(P, U, d, base, phi - 3 + j, st[j]);
+                for (int j = 0; j < 6; ++j) load_cell(P, U, d, base, phi - 3 + j, st[j], P.time);
                 Decision dec[10];
                 face_flux(P, d, st, alpha[d], fl[side], dump ? dec : nullptr);
                 if (dump) {
@@ -604,6 +650,13 @@ void rhs_cells_impl(const OrParams& P, const double* U, const double alpha[3],
                 }
             }
             for (int q = 0; q < nc; ++q) r[q] = r[q] - (fl[1][q] - fl[0][q]) / P.dx[d];
+        }
+        if (P.has_ext) {
+            int64_t N = ncells(P);
+            for (int dd = 0; dd < nd; ++dd) r[1 + dd] = r[1 + dd] + U[ci] * P.gravity[dd];
+            double sE = U[1 * N + ci] * P.gravity[0];
+            for (int dd = 1; dd < nd; ++dd) sE = sE + U[(1 + dd) * N + ci] * P.gravity[dd];
+            r[nc - 1] = r[nc - 1] + sE;
         }
         for (int q = 0; q < nc; ++q) out[s * nc + q] = r[q];
     }
@@ -689,7 +742,7 @@ int or_rhs(const OrParams* P, const double* U, const double* alpha3,
         a[1] = alpha3[1];
         a[2] = alpha3[2];
     }
-    rhs_impl<double>(*P, U, a, dUdt, dump);
+    rhs_impl<double>(*P, U, a, dUdt, dump, P->time);
     return st;
 }
 
@@ -706,7 +759,7 @@ int or_rhs_jvp(const OrParams* P, const double* U, const double* V,
     int64_t tot = ncells(*P) * (P->ndim + 2);
     std::vector<Dual> X((size_t)tot), Y((size_t)tot);
     for (int64_t i = 0; i < tot; ++i) X[(size_t)i] = Dual{U[i], V[i]};
-    rhs_impl<Dual>(*P, X.data(), alpha3, Y.data(), nullptr);
+    rhs_impl<Dual>(*P, X.data(), alpha3, Y.data(), nullptr, P->time);
     for (int64_t i = 0; i < tot; ++i) {
         if (dUdt) dUdt[i] = Y[(size_t)i].v;
         JV[i] = Y[(size_t)i].d;
@@ -735,7 +788,8 @@ int or_step(const OrParams* P, double* U, double cfl, double* t, double t_end,
         for (int k = 0; k < 3; ++k) alpha9[k] = a[k];
     }
     double h = *dt;
-    rhs_impl<double>(*P, U, a, Lv.data(), nullptr);
+    /* stage times t, t + h, t + h/2 (for time-dependent boundaries) */
+    rhs_impl<double>(*P, U, a, Lv.data(), nullptr, *t);
     for (int64_t i = 0; i < tot; ++i) U1[(size_t)i] = U[i] + h * Lv[(size_t)i];
     /* Stage 2. */
     if (replay) {
@@ -745,7 +799,7 @@ int or_step(const OrParams* P, double* U, double cfl, double* t, double t_end,
         status |= st;
         for (int k = 0; k < 3; ++k) alpha9[3 + k] = a[k];
     }
-    rhs_impl<double>(*P, U1.data(), a, Lv.data(), nullptr);
+    rhs_impl<double>(*P, U1.data(), a, Lv.data(), nullptr, *t + h);
     for (int64_t i = 0; i < tot; ++i)
         U2[(size_t)i] = (0.75 * U[i] + 0.25 * U1[(size_t)i]) + 0.25 * (h * Lv[(size_t)i]);
     /* Stage 3. */
@@ -756,7 +810,7 @@ int or_step(const OrParams* P, double* U, double cfl, double* t, double t_end,
         status |= st;
         for (int k = 0; k < 3; ++k) alpha9[6 + k] = a[k];
     }
-    rhs_impl<double>(*P, U2.data(), a, Lv.data(), nullptr);
+    rhs_impl<double>(*P, U2.data(), a, Lv.data(), nullptr, *t + 0.5 * h);
     for (int64_t i = 0; i < tot; ++i)
         U[i] = (T1_3 * U[i] + T2_3 * U2[(size_t)i]) + T2_3 * (h * Lv[(size_t)i]);
     *t = *t + h;
@@ -770,17 +824,19 @@ int or_run_jvp(const OrParams* P, double* U, double* V, int64_t nsteps,
     int64_t tot = ncells(*P) * (P->ndim + 2);
     std::vector<Dual> X((size_t)tot), X1((size_t)tot), X2((size_t)tot), Lv((size_t)tot);
     for (int64_t i = 0; i < tot; ++i) X[(size_t)i] = Dual{U[i], V[i]};
+    double t = P->time;
     for (int64_t k = 0; k < nsteps; ++k) {
         double h = dts[k];
         const double* a = alphas + 9 * k;
-        rhs_impl<Dual>(*P, X.data(), a, Lv.data(), nullptr);
+        rhs_impl<Dual>(*P, X.data(), a, Lv.data(), nullptr, t);
         for (int64_t i = 0; i < tot; ++i) X1[(size_t)i] = X[(size_t)i] + h * Lv[(size_t)i];
-        rhs_impl<Dual>(*P, X1.data(), a + 3, Lv.data(), nullptr);
+        rhs_impl<Dual>(*P, X1.data(), a + 3, Lv.data(), nullptr, t + h);
         for (int64_t i = 0; i < tot; ++i)
             X2[(size_t)i] = (0.75 * X[(size_t)i] + 0.25 * X1[(size_t)i]) + 0.25 * (h * Lv[(size_t)i]);
-        rhs_impl<Dual>(*P, X2.data(), a + 6, Lv.data(), nullptr);
+        rhs_impl<Dual>(*P, X2.data(), a + 6, Lv.data(), nullptr, t + 0.5 * h);
         for (int64_t i = 0; i < tot; ++i)
             X[(size_t)i] = (T1_3 * X[(size_t)i] + T2_3 * X2[(size_t)i]) + T2_3 * (h * Lv[(size_t)i]);
+        t = t + h;
     }
     for (int64_t i = 0; i < tot; ++i) {
         U[i] = X[(size_t)i].v;

@@ -15,9 +15,35 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
+
+
+@dataclasses.dataclass
+class Side:
+    """One end of an axis.  Ghost cells take kind_a where the split coordinate
+    (the cell centre (i + 1/2) dx along split_axis, measured from the grid's
+    low corner, on the boundary line) lies below split0 + split_rate * t, and
+    kind_b elsewhere; split_axis = -1 means kind_a everywhere.  Kinds:
+    "periodic", "transmissive", "reflective", "fixed" (the conserved state
+    state_a / state_b)."""
+    kind_a: str
+    kind_b: Optional[str] = None
+    split_axis: int = -1
+    split0: float = 0.0
+    split_rate: float = 0.0
+    state_a: Optional[Sequence[float]] = None
+    state_b: Optional[Sequence[float]] = None
+
+
+@dataclasses.dataclass
+class Boundary:
+    """Per-end boundaries sides[axis][0 low / 1 high], a gravity source
+    (momentum += rho g, energy += m . g) and the time of RHS evaluations."""
+    sides: list
+    gravity: Sequence[float] = (0.0, 0.0, 0.0)
+    time: float = 0.0
 
 
 @dataclasses.dataclass
@@ -39,6 +65,7 @@ class Problem:
     cr: float = 0.25
     xi: float = 1e-3
     x0: List[float] = dataclasses.field(default_factory=lambda: [0.0, 0.0, 0.0])
+    boundary: Optional[Boundary] = None   # per-end boundaries and gravity (Sec. 4.3)
 
     @property
     def nc(self) -> int:
@@ -174,6 +201,71 @@ def riemann_2d(n: int = 2048, states=RIEMANN2D_CONFIG3, split=(0.8, 0.8), ny=Non
         for c in range(4):
             out[c][m] = states[q][c]
     U = conserved(out[0], [out[1], out[2]], out[3], prob.gamma)
+    return prob, _as_field(prob, U)
+
+
+def riemann_2d_table2(case: int, n: int = 1024, **kw):
+    """The 2D Riemann problems timed in Table 2: case 1 = eq 4.14
+    (configuration 3), case 2 = eq 4.13 (configuration 12), quadrants split
+    at (0.5, 0.5) on [0, 1]^2, transmissive."""
+    states = RIEMANN2D_CONFIG3 if case == 1 else RIEMANN2D_CONFIG12
+    return riemann_2d(n, states=states, split=(0.5, 0.5), **kw)
+
+
+# --------------------------------------------------------------------------
+# Rayleigh-Taylor instability (Sec. 4.3, eq 4.12) and double Mach reflection
+# --------------------------------------------------------------------------
+def rayleigh_taylor(nx: int = 128, ny: int = 512, gamma: float = 5.0 / 3.0, **kw):
+    """[0, 0.25] x [0, 1], heavy fluid below y = 1/2, v perturbed by
+    -0.025 c cos(8 pi x) (c the sound speed), gravity source (0, 1) on
+    (rho v, E) as (rho, rho v); reflective left / right, fixed states
+    (rho, u, v, p) = (2, 0, 0, 1) below and (1, 0, 0, 2.5) above."""
+    prob = uniform_problem(2, [nx, ny], [0.0, 0.0], [0.25, 1.0], "reflective", gamma=gamma, **kw)
+    x = prob.centres(0)[None, :]
+    y = prob.centres(1)[:, None]
+    low = y < 0.5
+    rho = np.where(low, 2.0, 1.0) + 0.0 * x
+    p = np.where(low, 2.0 * y + 1.0, y + 1.5) + 0.0 * x
+    c = np.sqrt(gamma * p / rho)
+    v = -0.025 * c * np.cos(8.0 * math.pi * x)
+    U = conserved(rho, [np.zeros_like(rho), v], p, gamma)
+    bottom = conserved(2.0, [0.0, 0.0], 1.0, gamma).tolist()
+    top = conserved(1.0, [0.0, 0.0], 2.5, gamma).tolist()
+    bnd = Boundary(sides=[[Side("reflective"), Side("reflective")],
+                          [Side("fixed", state_a=bottom), Side("fixed", state_a=top)],
+                          [Side("periodic"), Side("periodic")]],
+                   gravity=(0.0, 1.0, 0.0))
+    prob = prob.replace(boundary=bnd)
+    return prob, _as_field(prob, U)
+
+
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)   # (rho, u, v, p) ahead of the Mach-10 shock
+DMR_POST = (8.0, 8.25 * math.cos(math.pi / 6.0), -8.25 * math.sin(math.pi / 6.0), 116.5)
+
+
+def double_mach(nx: int = 1024, ny: int = 256, **kw):
+    """[0, 4] x [0, 1]: a Mach-10 shock inclined at 60 degrees through
+    (1/6, 0) moving right; reflecting wall from x = 1/6 on the bottom (fixed
+    post-shock state before it), post-shock inflow on the left, zero-gradient
+    outflow on the right, and a top boundary that follows the exact shock
+    position x = 1/6 + (1 + 20 t) / sqrt(3)."""
+    prob = uniform_problem(2, [nx, ny], [0.0, 0.0], [4.0, 1.0], "transmissive", **kw)
+    g = prob.gamma
+    x = prob.centres(0)[None, :]
+    y = prob.centres(1)[:, None]
+    post = x < 1.0 / 6.0 + y / math.sqrt(3.0)
+    prim = [np.where(post, DMR_POST[k], DMR_PRE[k]) for k in range(4)]
+    U = conserved(prim[0], [prim[1], prim[2]], prim[3], g)
+    s_post = conserved(DMR_POST[0], [DMR_POST[1], DMR_POST[2]], DMR_POST[3], g).tolist()
+    s_pre = conserved(DMR_PRE[0], [DMR_PRE[1], DMR_PRE[2]], DMR_PRE[3], g).tolist()
+    r3 = math.sqrt(3.0)
+    bnd = Boundary(sides=[
+        [Side("fixed", state_a=s_post), Side("transmissive")],
+        [Side("fixed", "reflective", split_axis=0, split0=1.0 / 6.0, state_a=s_post),
+         Side("fixed", "fixed", split_axis=0, split0=1.0 / 6.0 + 1.0 / r3, split_rate=20.0 / r3,
+              state_a=s_post, state_b=s_pre)],
+        [Side("periodic"), Side("periodic")]])
+    prob = prob.replace(boundary=bnd)
     return prob, _as_field(prob, U)
 
 

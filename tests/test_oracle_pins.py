@@ -6,6 +6,7 @@ LAD mapping (Sec. 3 eq 3.1-3.2), algebraic identities of the characteristic
 decomposition, conservation / free-stream / symmetry invariants and the exact
 Riemann solution.  No GPU is needed.
 """
+import dataclasses
 import math
 import os
 
@@ -514,3 +515,111 @@ def test_teno5a_cutoff_range_and_symmetry(orc):
         assert 5 <= mr <= 10
         seen_rt.add(mr)
     assert seen == {7, 8, 9, 10} and len(seen_rt) >= 5
+
+
+# --------------------------------------------------------------------------
+# Per-end boundaries, moving splits and the gravity source (Sec. 4.3)
+# --------------------------------------------------------------------------
+def _uniform2d(nx, ny, prim, boundary, bc="periodic"):
+    prob = W.uniform_problem(2, [nx, ny], [0.0, 0.0], [1.0, 0.8], bc).replace(boundary=boundary)
+    rho, u, v, p = prim
+    U = W.conserved(np.full((ny, nx), rho), [np.full((ny, nx), u), np.full((ny, nx), v)],
+                    np.full((ny, nx), p), prob.gamma)
+    return prob, np.ascontiguousarray(U.reshape(prob.shape))
+
+
+def _sides(lo_y, hi_y, x="periodic"):
+    return [[W.Side(x), W.Side(x)], [lo_y, hi_y], [W.Side("periodic"), W.Side("periodic")]]
+
+
+def test_gravity_source_on_uniform_state(orc):
+    # Uniform state: every flux difference vanishes exactly, so the RHS is
+    # the source alone: (0, rho g_x, rho g_y, m_x g_x + m_y g_y).
+    g = (0.3, -0.7, 0.0)
+    bnd = W.Boundary(sides=_sides(W.Side("periodic"), W.Side("periodic")), gravity=g)
+    prob, U = _uniform2d(12, 10, (1.3, 0.2, -0.1, 0.9), bnd)
+    R = orc.rhs(prob, U)
+    rho, mx, my = U[0], U[1], U[2]
+    assert np.all(R[0] == 0.0)
+    assert np.array_equal(R[1], rho * g[0]) and np.array_equal(R[2], rho * g[1])
+    assert np.array_equal(R[3], mx * g[0] + my * g[1])
+
+
+def test_fixed_boundary_states(orc):
+    prim = (1.1, 0.3, 0.0, 0.8)
+    state = W.conserved(prim[0], [prim[1], prim[2]], prim[3], 1.4).tolist()
+    other = W.conserved(0.7, [0.1, -0.2], 0.5, 1.4).tolist()
+    # a fixed ghost state equal to the interior keeps the free stream
+    bnd = W.Boundary(sides=_sides(W.Side("fixed", state_a=state), W.Side("fixed", state_a=state)))
+    prob, U = _uniform2d(9, 11, prim, bnd)
+    R = orc.rhs(prob, U)
+    assert np.all(R == 0.0)
+    # another state below reaches exactly the first three rows (5-point
+    # stencils, 3 ghost layers) and nothing else
+    bnd = W.Boundary(sides=_sides(W.Side("fixed", state_a=other), W.Side("fixed", state_a=state)))
+    prob, U = _uniform2d(9, 11, prim, bnd)
+    R = orc.rhs(prob, U)
+    rows = np.nonzero(np.any(R != 0.0, axis=(0, 1, 3)))[0]
+    assert list(rows) == [0, 1, 2]
+
+
+def test_split_boundary_position_and_motion(orc):
+    # Interior at rest: a reflecting wall keeps it at rest, a fixed different
+    # state does not.  The bottom is fixed for cell centres x < 0.3 + 0.5 t
+    # and reflecting beyond, so the disturbed columns are exactly those with
+    # (i + 1/2) dx < 0.3 + 0.5 t.
+    prim = (1.0, 0.0, 0.0, 1.0)
+    other = W.conserved(2.0, [0.0, 0.0], 3.0, 1.4).tolist()
+    nx = 20
+    dx = 1.0 / nx
+    for t in (0.0, 0.21, 0.9):
+        bnd = W.Boundary(sides=_sides(W.Side("fixed", "reflective", split_axis=0, split0=0.3,
+                                              split_rate=0.5, state_a=other),
+                                       W.Side("reflective"), x="reflective"), time=t)
+        prob, U = _uniform2d(nx, 8, prim, bnd)
+        R = orc.rhs(prob, U)
+        cols = np.nonzero(np.any(R != 0.0, axis=(0, 1, 2)))[0]
+        expect = [i for i in range(nx) if (i + 0.5) * dx < 0.3 + 0.5 * t]
+        assert list(cols) == expect, (t, cols, expect)
+
+
+def test_double_mach_states_satisfy_rankine_hugoniot():
+    # Mach 10 into (1.4, 0, 0, 1) (sound speed 1): in the frame of the shock
+    # (normal speed 10) mass, momentum and energy fluxes match across it, the
+    # post-shock velocity 8.25 lying along the shock normal (30 degrees below x).
+    g = 1.4
+    r1, u1, v1, p1 = W.DMR_PRE
+    r2, u2, v2, p2 = W.DMR_POST
+    assert abs(math.sqrt(g * p1 / r1) - 1.0) < 1e-15
+    s = 10.0
+    w2 = u2 * math.cos(math.pi / 6.0) - v2 * math.sin(math.pi / 6.0)
+    assert abs(w2 - 8.25) < 1e-12 and abs(u2 * math.sin(math.pi / 6) + v2 * math.cos(math.pi / 6)) < 1e-12
+    assert abs(r1 * s - r2 * (s - w2)) < 1e-12
+    assert abs((r1 * s * s + p1) - (r2 * (s - w2) ** 2 + p2)) < 1e-10
+    h1 = g / (g - 1.0) * p1 / r1
+    h2 = g / (g - 1.0) * p2 / r2
+    assert abs((0.5 * s * s + h1) - (0.5 * (s - w2) ** 2 + h2)) < 1e-10
+
+
+def test_rayleigh_taylor_layers_are_hydrostatic(orc):
+    # Without the velocity perturbation each layer has p linear in y with
+    # dp/dy = rho, balanced by the source rho g (g = 1): the fluxes are
+    # linear, reconstructed exactly, so the vertical-momentum RHS vanishes
+    # (to round-off) away from the interface and the fixed ends.
+    prob, U = W.rayleigh_taylor(16, 64)
+    U0 = U.copy()
+    U0[2] = 0.0
+    U0[3] = U[3] - 0.5 * U[2] ** 2 / U[0]
+    R = orc.rhs(prob, U0)
+    y = prob.centres(1)
+    ny = len(y)
+    interior = [j for j in range(4, ny - 4) if abs(y[j] - 0.5) > 4 * prob.dx[1]]
+    assert np.abs(R[2][0][interior]).max() < 1e-11
+    assert np.abs(R[0][0][interior]).max() < 1e-11
+    # the source is what balances it: without gravity the same rows see -dp/dy
+    nograv = dataclasses.replace(prob.boundary, gravity=(0.0, 0.0, 0.0))
+    R0 = orc.rhs(prob.replace(boundary=nograv), U0)
+    low = [j for j in interior if y[j] < 0.5]
+    high = [j for j in interior if y[j] > 0.5]
+    assert np.allclose(R0[2][0][low], -2.0, atol=1e-10)
+    assert np.allclose(R0[2][0][high], -1.0, atol=1e-10)
