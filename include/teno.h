@@ -57,6 +57,35 @@ extern "C" {
 #define TENO_BC_PERIODIC 0
 #define TENO_BC_TRANSMISSIVE 1
 #define TENO_BC_REFLECTIVE 2
+/* A fixed ghost state (only through teno_boundary below): the Dirichlet ends
+ * of the Rayleigh-Taylor and double Mach reflection problems of Sec. 4.3. */
+#define TENO_BC_FIXED 3
+
+/* One end of an axis whose boundary may change along the boundary and in
+ * time.  Its ghost cells take kind[0] where the split coordinate -- the cell
+ * centre (i + 1/2) dx along axis split_axis, measured from the grid's low
+ * corner, on the boundary line -- lies below split[0] + split[1] * t, and
+ * kind[1] elsewhere (split_axis = -1: kind[0] everywhere).  A TENO_BC_FIXED
+ * part supplies state[part] (conserved variables, natural order, ncomp used). */
+typedef struct teno_side {
+    int32_t kind[2];      /* TENO_BC_*                                            */
+    int32_t split_axis;   /* 0, 1, 2, or -1                                       */
+    int32_t reserved_;
+    double split[2];      /* split position split[0] + split[1] * t               */
+    double state[2][5];   /* fixed ghost states                                   */
+} teno_side;
+
+/* Per-end boundaries, a gravity source and the time of teno_rhs calls, in
+ * DEVICE memory (read by the kernels).  Boundaries are evaluated at the
+ * stage times t, t + dt, t + dt/2 of teno_step and at t_rhs by teno_rhs.
+ * The source adds rho g_d to each momentum component and sum_d m_d g_d to
+ * the energy after the flux differences (Sec. 4.3: rho and rho v for the
+ * Rayleigh-Taylor problem, g = (0, 1)). */
+typedef struct teno_boundary {
+    teno_side side[3][2]; /* [axis][0: low end, 1: high end]                      */
+    double gravity[3];
+    double t_rhs;
+} teno_boundary;
 
 /* Cutoff schemes: the locally adaptive C_T (Sec. 3), a fixed C_T (TENO5,
  * Sec. 2 eq 2.14), or every stencil kept (the linear upwind scheme eq 2.3). */
@@ -88,6 +117,10 @@ typedef struct teno_grid {
                           0 <= a1 - a2, a1 <= 20                                */
     double cr;         /* TENO5-A C_r of eq 2.17 (paper: 0.25); 0 < 0.9 cr < 1  */
     double xi;         /* TENO5-A xi of eq 2.18 (paper: 1e-3); >= 0             */
+    const teno_boundary* boundary_dev; /* nullable: per-end boundaries and gravity
+                          (device memory); when set, bc[] is not used.  Not
+                          supported by the adjoint and batched entry points
+                          (TENO_ERR_ARG)                                        */
 } teno_grid;
 
 /* teno_grid.flags: evaluate every cutoff decision with the literal formula

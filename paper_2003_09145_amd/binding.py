@@ -18,7 +18,26 @@ LIB_PATH = os.path.join(_HERE, "libteno.so")
 
 OK, ERR_ARG, ERR_DEVICE, ERR_NONPHYSICAL = 0, 1, 2, 3
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+BC_FIXED = 3
 SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
+
+
+class TenoSide(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32 * 2),
+        ("split_axis", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
+        ("split", ctypes.c_double * 2),
+        ("state", ctypes.c_double * 10),
+    ]
+
+
+class TenoBoundary(ctypes.Structure):
+    _fields_ = [
+        ("side", TenoSide * 6),   # [axis][end]
+        ("gravity", ctypes.c_double * 3),
+        ("t_rhs", ctypes.c_double),
+    ]
 
 
 class TenoGrid(ctypes.Structure):
@@ -40,6 +59,7 @@ class TenoGrid(ctypes.Structure):
         ("a2", ctypes.c_double),
         ("cr", ctypes.c_double),
         ("xi", ctypes.c_double),
+        ("boundary_dev", ctypes.c_void_p),
     ]
 
 
@@ -183,7 +203,41 @@ def grid(prob) -> TenoGrid:
     g.xi = float(_get(prob, "xi", 1e-3))
     g.flags = ((FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0) |
                (FLAG_MASK_DIGEST if _get(prob, "mask_digest", False) else 0))
+    bnd = _get(prob, "boundary", None)
+    if bnd is not None:
+        g.boundary_buf = boundary_device(bnd)   # keeps the device copy alive
+        g.boundary_dev = g.boundary_buf.data_ptr()
     return g
+
+
+def boundary_struct(bnd) -> TenoBoundary:
+    """teno_boundary from a workloads.Boundary description."""
+    kinds = dict(BC, fixed=BC_FIXED)
+    b = TenoBoundary()
+    for d in range(3):
+        for e in range(2):
+            sd = bnd.sides[d][e]
+            o = b.side[d * 2 + e]
+            o.kind[0] = kinds[sd.kind_a]
+            o.kind[1] = kinds[sd.kind_b] if sd.kind_b is not None else o.kind[0]
+            o.split_axis = int(sd.split_axis)
+            o.split[0] = float(sd.split0)
+            o.split[1] = float(sd.split_rate)
+            for w, st in enumerate((sd.state_a, sd.state_b)):
+                if st is not None:
+                    for q, v in enumerate(st):
+                        o.state[w * 5 + q] = float(v)
+    for k in range(3):
+        b.gravity[k] = float(bnd.gravity[k])
+    b.t_rhs = float(bnd.time)
+    return b
+
+
+def boundary_device(bnd, device="cuda"):
+    """The teno_boundary of a description in a device uint8 tensor."""
+    import torch
+    host = bytes(boundary_struct(bnd))
+    return torch.frombuffer(bytearray(host), dtype=torch.uint8).to(device)
 
 
 def _ptr(t):

@@ -566,7 +566,8 @@ size_t teno_adjoint_workspace_bytes(const teno_grid* g) {
 int teno_rhs_adjoint(const teno_grid* g, const double* U, const double* alpha, const double* lam,
                      double* gradU, void* ws, size_t ws_bytes, void* stream) {
     if (validate(g) != TENO_OK || U == nullptr || alpha == nullptr || lam == nullptr ||
-        gradU == nullptr || ws == nullptr || ws_bytes < adj_ws_bytes(g))
+        gradU == nullptr || ws == nullptr || ws_bytes < adj_ws_bytes(g) ||
+        g->boundary_dev != nullptr)
         return TENO_ERR_ARG;
     double* G = (double*)((char*)ws + 6 * adj_state_bytes(g));
     return rhs_adjoint_impl(g, U, alpha, lam, gradU, G, (hipStream_t)stream) == hipSuccess
@@ -577,7 +578,7 @@ int teno_rhs_adjoint(const teno_grid* g, const double* U, const double* alpha, c
 int teno_step_adjoint(const teno_grid* g, const double* Un, const teno_ctrl* ctrl, double* lam,
                       void* ws, size_t ws_bytes, void* stream) {
     if (validate(g) != TENO_OK || Un == nullptr || ctrl == nullptr || lam == nullptr ||
-        ws == nullptr || ws_bytes < adj_ws_bytes(g))
+        ws == nullptr || ws_bytes < adj_ws_bytes(g) || g->boundary_dev != nullptr)
         return TENO_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     const size_t sb = adj_state_bytes(g);

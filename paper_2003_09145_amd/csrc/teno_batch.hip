@@ -419,7 +419,7 @@ int teno_batch_plan_create(const teno_grid* g, int64_t nbatch, const int64_t* le
                            const double* dx, double cfl, double t_end, const char* tune_cache,
                            teno_batch_plan** out) {
     if (out == nullptr || g == nullptr || lengths == nullptr || dx == nullptr || nbatch <= 0 ||
-        nbatch > 0x7fffffff || !(cfl > 0.0) || !(t_end > 0.0))
+        nbatch > 0x7fffffff || !(cfl > 0.0) || !(t_end > 0.0) || g->boundary_dev != nullptr)
         return TENO_ERR_ARG;
     teno_grid gg = *g;
     gg.ndim = 1;

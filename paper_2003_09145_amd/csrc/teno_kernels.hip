@@ -59,7 +59,40 @@ struct SweepArgs {
     double dx;
     SchemeParams sch;
     DecisionConsts dk;
+    const teno_boundary* bnd;  // nullable: per-end boundaries and gravity
+    int32_t add_source;        // 1 on the last axis when bnd is set
+    int32_t nx, ny;            // grid sizes (boundary split coordinates)
+    double dxa[3];             // spacings per axis (boundary split coordinates)
 };
+
+// Boundary kind of the ghost cells at end `end` of axis `dir` for the line
+// whose interior cells start at global index cell0 (per-end boundaries): the
+// split coordinate along the side's split axis, the split position at the
+// stage time (teno_step: t, t + dt, t + dt/2 by stage; teno_rhs: t_rhs), and
+// the fixed state when the selected part is TENO_BC_FIXED (*fixed, else null).
+__device__ __forceinline__ int boundary_kind(const teno_boundary* bnd, const teno_ctrl* ctrl,
+                                             int stage, int dir, int end, int64_t cell0, int nx,
+                                             int ny, const double* dxa, const double** fixed) {
+    const teno_side* sd = &bnd->side[dir][end];
+    int which = 0;
+    const int ax = sd->split_axis;
+    if (ax >= 0) {
+        const int64_t nxy = (int64_t)nx * ny;
+        const int64_t ia = (ax == 0) ? cell0 % nx : (ax == 1) ? (cell0 / nx) % ny : cell0 / nxy;
+        double t = bnd->t_rhs;
+        if (ctrl != nullptr) {
+            t = ctrl->t;
+            if (stage == 1) t = ctrl->t + ctrl->dt;
+            if (stage == 2) t = ctrl->t + 0.5 * ctrl->dt;
+        }
+        const double coord = ((double)ia + 0.5) * dxa[ax];
+        const double split = sd->split[0] + sd->split[1] * t;
+        if (!(coord < split)) which = 1;
+    }
+    const int kind = sd->kind[which];
+    *fixed = (kind == TENO_BC_FIXED) ? sd->state[which] : nullptr;
+    return kind;
+}
 
 // Map the hardware block index to a logical index such that blocks that run
 // on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
@@ -150,13 +183,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int bw = jq / (int)np6;
         const int64_t b = be0 + bw;
         const int j = jq - bw * (int)np6 - 3;
-        bool flip;
-        const int src = ghost_src(A.bc, n, j, &flip);
-        const int64_t cell = colbase_c + b * A.line_step + (int64_t)src * A.stride;
+        bool flip = false;
+        int kind = A.bc;
+        const double* fixed = nullptr;
+        if (A.bnd != nullptr && (j < 0 || j >= n))
+            kind = boundary_kind(A.bnd, A.ctrl, A.stage, DIR, j < 0 ? 0 : 1,
+                                 colbase_c + b * A.line_step, A.nx, A.ny, A.dxa, &fixed);
         double q[NC];
+        if (fixed != nullptr) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
-        if (flip) q[1 + DIR] = -q[1 + DIR];
+            for (int c = 0; c < NC; ++c) q[c] = fixed[c];
+        } else {
+            const int src = ghost_src(kind, n, j, &flip);
+            const int64_t cell = colbase_c + b * A.line_step + (int64_t)src * A.stride;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
+            if (flip) q[1 + DIR] = -q[1 + DIR];
+        }
         stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, idx);
     }
     }
@@ -228,6 +271,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
             const double diff = fh_c[c * 64 + jj] - fh_c[c * 64 + jj - 1];
             const double prev = (A.Rin != nullptr) ? A.Rin[c * A.ncell + cell] : 0.0;
             r[c] = prev - cr_div_r(diff, A.dx, rdx);
+        }
+        if (A.add_source) {
+            // gravity: rho g_d on each momentum, m . g on the energy (after the
+            // flux differences of every axis)
+            const double* g = A.bnd->gravity;
+            const double rho = A.U[cell];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) r[1 + d] = r[1 + d] + rho * g[d];
+            double sE = A.U[1 * A.ncell + cell] * g[0];
+#pragma unroll
+            for (int d = 1; d < ND; ++d) sE = sE + A.U[(1 + d) * A.ncell + cell] * g[d];
+            r[NC - 1] = r[NC - 1] + sE;
         }
         if (A.rk == 0) {
 #pragma unroll
@@ -526,6 +581,11 @@ static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStre
     A.bc = g->bc[dir];
     A.dx = g->dx[dir];
     A.ncell = ncell_of(g);
+    A.bnd = g->boundary_dev;
+    if (A.bnd == nullptr) A.add_source = 0;
+    A.nx = nx;
+    A.ny = ny;
+    for (int k = 0; k < 3; ++k) A.dxa[k] = g->dx[k];
     A.sch = scheme_of(g);
     A.dk = decision_consts(g, A.dump != nullptr);
     A.ext_cap = ext_cap_for(n);
@@ -610,6 +670,7 @@ static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const d
         A.alpha = S->alpha_used;
         A.dump = dump ? dump + dump_off : nullptr;
         A.rk = 0;
+        A.add_source = (d == g->ndim - 1) ? 1 : 0;
         if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;
         dump_off += ncell_of(g) / g->n[d] * (int64_t)(g->n[d] + 1) * 2 * (g->ndim + 2);
     }
@@ -744,6 +805,7 @@ static int step_impl(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, s
                 A.rk = s + 1;
                 A.Un = U;
                 A.Uout = stage_out[s];
+                A.add_source = 1;
             }
             void* ev0 = events ? events[2 * (3 * s + d)] : nullptr;
             void* ev1 = events ? events[2 * (3 * s + d) + 1] : nullptr;

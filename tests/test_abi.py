@@ -53,6 +53,8 @@ int main(void) {
          offsetof(teno_grid, bc), offsetof(teno_grid, gamma), offsetof(teno_grid, H),
          offsetof(teno_grid, Bl), offsetof(teno_grid, eps), offsetof(teno_grid, flags),
          offsetof(teno_grid, a1), offsetof(teno_grid, xi));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(teno_side), sizeof(teno_boundary),
+         offsetof(teno_boundary, gravity), offsetof(teno_side, state), offsetof(teno_grid, boundary_dev));
   printf("%zu %zu %zu %zu %zu\n", sizeof(teno_ctrl), offsetof(teno_ctrl, alpha),
          offsetof(teno_ctrl, status), offsetof(teno_ctrl, nsteps), offsetof(teno_ctrl, active));
   return 0;
@@ -65,7 +67,11 @@ int main(void) {
     assert [int(x) for x in out[0].split()] == [
         ctypes.sizeof(G), G.dx.offset, G.bc.offset, G.gamma.offset, G.H.offset, G.Bl.offset,
         G.eps.offset, G.flags.offset, G.a1.offset, G.xi.offset]
+    Sd, Bd = B.TenoSide, B.TenoBoundary
     assert [int(x) for x in out[1].split()] == [
+        ctypes.sizeof(Sd), ctypes.sizeof(Bd), Bd.gravity.offset, Sd.state.offset,
+        G.boundary_dev.offset]
+    assert [int(x) for x in out[2].split()] == [
         ctypes.sizeof(C), C.alpha.offset, C.status.offset, C.nsteps.offset, C.active.offset]
 
 
