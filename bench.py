@@ -18,6 +18,9 @@ Beside the headline the same JSON line carries
                 TENO5-LAD against fixed-cutoff TENO5, TENO5-A (eq 2.16-2.18)
                 and the linear upwind scheme, next to the per-step times of
                 Table 2;
+  table2        the 2D workloads of Table 2 (Rayleigh-Taylor, the two 2D
+                Riemann problems, the double Mach reflection) per scheme,
+                next to the paper's CPU seconds per step;
   batched       4096 ragged 1D shock tubes (N log-uniform in [128, 4096]),
                 500 steps of the persistent graph-replayed batch kernel
                 against teno_step per tube on the same GPU;
@@ -270,6 +273,114 @@ def schemes_leg(args, B, W, torch):
           f"{base['rhs_ms']:.3f}, linear {out['linear5']['rhs_ms']:.3f} ms",
           file=sys.stderr, flush=True)
     return out
+
+
+# --------------------------------------------------------------------------
+# f3: the 2D workloads of Table 2, each scheme timed on the same GPU
+# --------------------------------------------------------------------------
+TABLE2 = [  # case, grid, builder, paper seconds per step (WENO-Z, TENO5, TENO5-A, Present)
+    ("Rayleigh-Taylor", "128x512", lambda W: W.rayleigh_taylor(128, 512), (0.14, 0.15, 0.2, 0.16)),
+    ("Rayleigh-Taylor", "256x1024", lambda W: W.rayleigh_taylor(256, 1024), (0.59, 0.67, 0.88, 0.70)),
+    ("2D Riemann case 1 (eq 4.14)", "1024x1024", lambda W: W.riemann_2d_table2(1, 1024),
+     (2.57, 2.89, 3.71, 2.99)),
+    ("2D Riemann case 2 (eq 4.13)", "1024x1024", lambda W: W.riemann_2d_table2(2, 1024),
+     (2.56, 2.85, 3.68, 2.99)),
+    ("2D Riemann case 2 (eq 4.13)", "2048x2048", lambda W: W.riemann_2d_table2(2, 2048),
+     (11.9, 13.1, 17.8, 13.7)),
+    ("Double Mach reflection", "1024x256", lambda W: W.double_mach(1024, 256),
+     (0.59, 0.66, 0.87, 0.69)),
+]
+
+
+def t_final_of(case):
+    """Final times of the Sec. 4.3 runs."""
+    if case.startswith("Rayleigh"):
+        return 1.95
+    if case.startswith("2D Riemann case 1"):
+        return 0.3
+    if case.startswith("2D Riemann case 2"):
+        return 0.25
+    if case.startswith("Double"):
+        return 0.2
+    return None
+
+
+def table2_leg(args, B, W, torch):
+    """Per-step time of TENO5-LAD, TENO5 and TENO5-A on the Table 2 workloads
+    (timed from the initial condition), with the parameter adjustments the
+    paper states: TENO5-A alpha_2 = 5.5, C_r = 0.3 for Riemann case 1 and the
+    double Mach reflection, TENO5 C_T = 1e-5 for the double Mach reflection;
+    TENO5 C_T = 1e-7 otherwise (Sec. 4)."""
+    rows = []
+    for case, grid_s, build, paper in TABLE2:
+        prob0, U = build(W)
+        Ud0 = torch.from_numpy(U).cuda()
+        dmr = case.startswith("Double")
+        adjust_a = case.startswith("2D Riemann case 1") or dmr
+        schemes = {
+            "lad": {},
+            "teno5": {"scheme": "fixed_ct", "ct_fixed": 1e-5 if dmr else 1e-7},
+            "teno5a": dict({"scheme": "teno5a"}, **({"a2": 5.5, "cr": 0.3} if adjust_a else {})),
+        }
+        row = {"case": case, "grid": grid_s,
+               "paper_s_per_step": dict(zip(("WENO-Z", "TENO5", "TENO5-A", "Present"), paper))}
+        for name, kw in schemes.items():
+            prob = prob0.replace(**kw)
+            S = B.Solver(prob)
+            Ud = Ud0.clone()
+            S.init(0.0, float("inf"), 0.5)
+            S.step(Ud)
+            Ud = Ud0.clone()
+            S.init(0.0, float("inf"), 0.5)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.table2_steps):
+                S.step(Ud)
+            e1.record()
+            torch.cuda.synchronize()
+            c = S.read_ctrl()
+            ok = c.status == 0 and c.nsteps == args.table2_steps
+            # steps after a non-physical state are no-ops: no valid timing then
+            row[name] = {"ms_per_step": (round(e0.elapsed_time(e1) / args.table2_steps, 4)
+                                         if ok else None),
+                         "status": int(c.status), "steps_done": int(c.nsteps)}
+        base = row["teno5"]["ms_per_step"]
+        row["ratio_to_teno5"] = {k: (round(row[k]["ms_per_step"] / base, 3)
+                                     if row[k]["ms_per_step"] and base else None)
+                                 for k in ("lad", "teno5", "teno5a")}
+        row["paper_ratio_to_teno5"] = {"lad": round(paper[3] / paper[1], 3),
+                                       "teno5a": round(paper[2] / paper[1], 3)}
+        if row["lad"]["ms_per_step"]:
+            row["speedup_vs_paper_present"] = round(paper[3] * 1e3 / row["lad"]["ms_per_step"], 1)
+        if t_final_of(case) is not None and grid_s in ("128x512", "1024x1024", "1024x256"):
+            # TENO5-LAD with the paper's parameters to the paper's final time
+            # (the double Mach reflection also with H = 1, see the notes)
+            runs = {"lad_full_run": {}}
+            if case.startswith("Double"):
+                runs["lad_H1_full_run"] = {"H": 1.0}
+            for key, kw in runs.items():
+                S = B.Solver(prob0.replace(**kw))
+                Ud = Ud0.clone()
+                S.init(0.0, t_final_of(case), 0.5)
+                w0 = time.perf_counter()
+                for k in range(100000):
+                    S.step(Ud)
+                    if k % 200 == 199:
+                        c = S.read_ctrl()
+                        if c.status != 0 or not c.t < t_final_of(case):
+                            break
+                c = S.read_ctrl()
+                row[key] = {"t_end": t_final_of(case), "t": c.t, "steps": int(c.nsteps),
+                            "status": int(c.status), "rho_min": float(Ud[0].min()),
+                            "wall_s": round(time.perf_counter() - w0, 3)}
+        rows.append(row)
+        fmt = lambda v: "n/a" if v is None else f"{v:.3f}"
+        print(f"[bench] table 2 {case} {grid_s}: LAD {fmt(row['lad']['ms_per_step'])} ms, "
+              f"TENO5 {fmt(base)} ms, TENO5-A {fmt(row['teno5a']['ms_per_step'])} ms",
+              file=sys.stderr, flush=True)
+    return {"steps": args.table2_steps, "cases": rows}
 
 
 # --------------------------------------------------------------------------
@@ -624,6 +735,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--table2-steps", type=int, default=10)
     ap.add_argument("--fd-cells", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -671,6 +783,7 @@ def main():
     }
     if not args.no_extras:
         out["schemes"] = schemes_leg(args, B, W, torch)
+        out["table2"] = table2_leg(args, B, W, torch)
         out["batched"] = batched_leg(args, B, W, torch)
         out["adjoint"] = adjoint_leg(args, B, W, torch)
     if not args.no_cpu_baseline:
