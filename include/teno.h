@@ -275,6 +275,27 @@ int teno_step_adjoint(const teno_grid* g, const double* Un_dev, const teno_ctrl*
                       double* lambda_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Scalar linear advection u_t + u_x = 0 (Sec. 4.1, eq 4.4) on a periodic 1D
+ * grid (g->ndim = 1; bc is not used, no boundary_dev), with the scheme of g:
+ * global Lax-Friedrichs splitting with alpha = 1 (f+ = u, f- = 0), each split
+ * flux reconstructed at every face by the scalar TENO5 of Sec. 2-3 (f- on the
+ * mirrored stencil), and the flux difference of eq 2.2.  The Table 1 test
+ * and the approximate dispersion relation of the scheme use it.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for teno_advect_step (three arrays of n doubles), 0 for an
+ * invalid grid. */
+size_t teno_advect_workspace_bytes(const teno_grid* g);
+
+/* dudt_dev = -(F_{i+1/2} - F_{i-1/2}) / dx for u_dev (n doubles each, device,
+ * not overlapping).  Enqueued on stream. */
+int teno_advect_rhs(const teno_grid* g, const double* u_dev, double* dudt_dev, void* stream);
+
+/* One SSP-RK3 step (eq 4.1-4.3) of size h >= 0, in place. */
+int teno_advect_step(const teno_grid* g, double* u_dev, double h, void* ws_dev,
+                     size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: nbatch independent 1D problems of uneven length, each with
  * its own LF speed, time step, time and status (the method of Sec. 2-4 per
  * problem).  Fields are packed component-major over the concatenated tubes:

@@ -92,6 +92,7 @@ SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_ctrl_replay", "teno_c
            "teno_rhs", "teno_rhs_debug", "teno_sweep",
            "teno_selftest_arith", "teno_step", "teno_step_timed",
            "teno_adjoint_workspace_bytes", "teno_rhs_adjoint", "teno_step_adjoint",
+           "teno_advect_workspace_bytes", "teno_advect_rhs", "teno_advect_step",
            "teno_batch_plan_create", "teno_batch_plan_destroy", "teno_batch_total_cells",
            "teno_batch_init", "teno_batch_step", "teno_batch_run", "teno_batch_autotune",
            "teno_batch_get_config", "teno_batch_set_config", "teno_batch_read"]
@@ -139,6 +140,12 @@ def lib():
         L.teno_rhs_adjoint.restype = ctypes.c_int
         L.teno_step_adjoint.argtypes = [G, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step_adjoint.restype = ctypes.c_int
+        L.teno_advect_workspace_bytes.argtypes = [G]
+        L.teno_advect_workspace_bytes.restype = ctypes.c_size_t
+        L.teno_advect_rhs.argtypes = [G, vp, vp, vp]
+        L.teno_advect_rhs.restype = ctypes.c_int
+        L.teno_advect_step.argtypes = [G, vp, ctypes.c_double, vp, ctypes.c_size_t, vp]
+        L.teno_advect_step.restype = ctypes.c_int
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         P = ctypes.c_void_p
         L.teno_batch_plan_create.argtypes = [G, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl), dbl,
@@ -334,6 +341,40 @@ def teno_step_adjoint(g, Un, ctrl, lam, ws, stream=None):
     _check(lib().teno_step_adjoint(ctypes.byref(g), _ptr(Un), _ptr(ctrl), _ptr(lam), _ptr(ws),
                                    ws.numel() * ws.element_size(), _stream(stream)),
            "teno_step_adjoint")
+
+
+def advect_grid(n: int, dx: float, scheme="lad", **kw) -> TenoGrid:
+    """Grid of the periodic scalar advection problem (Sec. 4.1)."""
+    return grid(dict(ndim=1, n=[n], dx=[dx], bc="periodic", scheme=scheme, **kw))
+
+
+def teno_advect_rhs(g, u, out, stream=None):
+    _check(lib().teno_advect_rhs(ctypes.byref(g), _ptr(u), _ptr(out), _stream(stream)),
+           "teno_advect_rhs")
+
+
+def teno_advect_step(g, u, h, ws, stream=None):
+    _check(lib().teno_advect_step(ctypes.byref(g), _ptr(u), float(h), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)),
+           "teno_advect_step")
+
+
+def advect_run(g, u, dt, t_end, stream=None):
+    """Fixed steps dt until t_end, the last one shortened to end at t_end;
+    returns the number of steps."""
+    import torch
+    ws = torch.empty(int(lib().teno_advect_workspace_bytes(ctypes.byref(g))), dtype=torch.uint8,
+                     device=u.device)
+    t = 0.0
+    steps = 0
+    while t < t_end:
+        h = dt
+        if t + h > t_end:
+            h = t_end - t
+        teno_advect_step(g, u, h, ws, stream)
+        t = t + h
+        steps += 1
+    return steps
 
 
 def decisions_bytes(g: TenoGrid) -> int:
