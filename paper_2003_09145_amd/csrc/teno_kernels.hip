@@ -169,16 +169,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double gm1 = A.sch.gamma - 1.0;
     const int64_t be0 = e_lo / np6;                 // line of the first ext cell (uniform)
     const int je0 = (int)(e_lo - be0 * np6);
-    // COOP (y and z sweeps, 4 waves = 4 neighbouring columns of one line chunk,
-    // which the host guarantees): thread t stages column t % 4, so a wave's
-    // loads cover 16 cells x 4 neighbouring x (16 cache lines, not 64).
-    constexpr bool COOP = (CAPC != 0) && (DIR != 0) && (W == 4);
+    // COOP (y and z sweeps, W waves = W neighbouring columns of one line chunk,
+    // which the host guarantees): thread t stages column t % W, so a wave's
+    // loads cover 64 / W cells x W neighbouring x (W = 16: whole cache lines).
+    constexpr bool COOP = (CAPC != 0) && (DIR != 0) && (W >= 4);
     const int64_t col0 = col - wave;  // first column of the block (uniform)
     {
-    const int cc = COOP ? (int)(threadIdx.x & 3) : wave;  // column slot within the block
+    const int cc = COOP ? (int)(threadIdx.x % W) : wave;  // column slot within the block
     const int64_t colbase_c = (col0 + cc) * A.col_step;
     double* ext_c = smem + 24 + (size_t)cc * per_wave;
-    for (int idx = COOP ? (int)(threadIdx.x >> 2) : lane; idx < count; idx += 64) {
+    for (int idx = COOP ? (int)(threadIdx.x / W) : lane; idx < count; idx += 64) {
         const int jq = je0 + idx;
         const int bw = jq / (int)np6;
         const int64_t b = be0 + bw;
@@ -245,20 +245,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     // ---- flux difference and epilogue ---------------------------------------
     // Face j of the chunk (j >= 1) updates its left cell from the fluxes at
-    // faces j and j - 1 (COOP: thread t updates column t % 4, face t / 4).
+    // faces j and j - 1 (COOP: thread t updates column t % W, face t / W).
     int jj = lane;
     int64_t blj = bl, phij = phi;
     bool upd = valid && lane > 0 && phi > 0;
     const double* fh_c = fhs;
     int64_t colbase_j = (DIR == 0) ? 0 : colbase;
     if constexpr (COOP) {
-        jj = (int)(threadIdx.x >> 2);
+        jj = (int)(threadIdx.x / W);
         const int tqj = phi0 + jj;
         const int wrj = tqj / (int)np1;
         blj = bl0 + wrj;
         phij = tqj - wrj * (int)np1;
         upd = F0 + jj < A.ftot && jj > 0 && phij > 0;
-        const int cc = (int)(threadIdx.x & 3);
+        const int cc = (int)(threadIdx.x % W);
         fh_c = smem + 24 + (size_t)cc * per_wave;
         colbase_j = (col0 + cc) * A.col_step;
     }
@@ -549,8 +549,9 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     const size_t per_wave =
         (size_t)((A.ext_cap * NV > 64 * NC) ? A.ext_cap * NV : 64 * NC) * sizeof(double);
     const size_t table = 24 * sizeof(double);
-    // the fixed-stride variant; along y and z it stages and updates four
-    // neighbouring columns per block, which needs whole blocks of columns
+    // the fixed-stride variant; along y and z a block stages and updates four
+    // neighbouring columns, which needs whole blocks of columns (8- and
+    // 16-column blocks, with 71 / 142 KB of LDS, measured no faster)
     if (!digest && A.ext_cap == kCapLong && (DIR == 0 || A.ncols % 4 == 0)) {
         const int64_t blocks = (A.nchunks + 3) / 4;
         hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong, A5>), dim3((unsigned)blocks),
