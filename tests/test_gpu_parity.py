@@ -377,3 +377,58 @@ def test_boundary_rejected_by_adjoint_and_batch(torch, B):
     assert L.teno_rhs_adjoint(ctypes.byref(g), d, d, d, d, d, 1 << 40, None) == B.ERR_ARG
     with pytest.raises(B.TenoError):
         B.BatchPlan([8, 9], [0.1, 0.1], prob={"boundary": prob.boundary})
+
+
+# --------------------------------------------------------------------------
+# A grid whose component offsets pass 2^31 and 2^32 (64-bit indexing)
+# --------------------------------------------------------------------------
+HASH_SALT = [(73856093, 19349663, 83492791), (2654435761, 40503, 97), (31, 1000003, 7919),
+             (2246822519, 3266489917, 668265263), (374761393, 16777619, 1299709)]
+
+
+def _hash_field_np(ii, jj, kk):
+    """Conserved state from an integer hash of the cell indices: every value
+    is a dyadic rational, so host and device build identical bits.
+    rho = 1 + h/1024, m_d = (h - 512)/4096, E = 2.5 + h/1024."""
+    out = []
+    for c, (a, b, cc) in enumerate(HASH_SALT):
+        h = ((ii * a) ^ (jj * b) ^ (kk * cc)) & 1023
+        h = h.astype(np.float64)
+        out.append(1.0 + h / 1024.0 if c == 0 else 2.5 + h / 1024.0 if c == 4 else (h - 512.0) / 4096.0)
+    return np.stack(out)
+
+
+def test_huge_grid_64bit_offsets(torch, B, orc):
+    nx, ny, nz = 1024, 1024, 832
+    ncell = nx * ny * nz
+    assert 4 * ncell + ncell > 2 ** 32
+    prob = W.uniform_problem(3, [nx, ny, nz], [0.0] * 3, [1.0, 1.0, 0.8], "periodic")
+    g = B.grid(prob)
+    U = torch.empty((5, nz, ny, nx), dtype=torch.float64, device="cuda")
+    i = torch.arange(nx, device="cuda", dtype=torch.int64).view(1, 1, nx)
+    j = torch.arange(ny, device="cuda", dtype=torch.int64).view(1, ny, 1)
+    for c, (a, b, cc) in enumerate(HASH_SALT):
+        for k0 in range(0, nz, 64):
+            k = torch.arange(k0, min(nz, k0 + 64), device="cuda", dtype=torch.int64).view(-1, 1, 1)
+            h = (((i * a) ^ (j * b) ^ (k * cc)) & 1023).to(torch.float64)
+            U[c, k0:k0 + k.shape[0]] = (1.0 + h / 1024.0 if c == 0 else 2.5 + h / 1024.0 if c == 4
+                                        else (h - 512.0) / 4096.0)
+    alpha = torch.tensor([2.0, 2.5, 3.0], dtype=torch.float64, device="cuda")
+    R = torch.empty_like(U)
+    for axis in range(3):
+        B.teno_sweep(g, axis, U, R, alpha, Rin=(R if axis else None))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    cells = [tuple(int(v) for v in (rng.integers(nx), rng.integers(ny), rng.integers(nz)))
+             for _ in range(40)]
+    cells += [(nx - 1, ny - 1, nz - 1), (0, ny - 1, nz - 1), (nx - 2, 3, nz - 1), (5, 0, 0)]
+    # the RHS of a cell needs its 7^3 neighbourhood only (3 cells per side)
+    box = W.Problem(ndim=3, n=[7, 7, 7], dx=list(prob.dx), bc=["periodic"] * 3)
+    off = np.arange(-3, 4)
+    idx = torch.tensor([[k, jy, ix] for ix, jy, k in cells], device="cuda")
+    got = R[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().T
+    for s, (ix, jy, k) in enumerate(cells):
+        kk, jj, ii = np.meshgrid((k + off) % nz, (jy + off) % ny, (ix + off) % nx, indexing="ij")
+        Ubox = np.ascontiguousarray(_hash_field_np(ii, jj, kk))
+        ref = orc.rhs_cells(box, Ubox, alpha.cpu().numpy(), np.array([3 * 49 + 3 * 7 + 3]))
+        assert np.array_equal(got[s], ref[0]), (ix, jy, k, got[s], ref[0])
