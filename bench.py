@@ -500,6 +500,23 @@ def adjoint_leg(args, B, W, torch):
     rhs_ms = timed(lambda: S.rhs(Ud, alpha_in=alpha, out=R))
     adj_ms = timed(lambda: B.teno_rhs_adjoint(rec.g, Ud, alpha, lam, G, rec.ws_adj))
 
+    # the same ratio on a 3D field (kernel-bound rather than launch-bound)
+    p3, U3 = W.turbulence_3d(args.adjoint_n3d, seed=0)
+    S3 = B.Solver(p3)
+    U3d = torch.from_numpy(U3).cuda()
+    R3 = S3.rhs(U3d)
+    a3 = S3.alpha.clone()
+    g3 = B.grid(p3)
+    ws3 = torch.empty(B.adjoint_workspace_bytes(g3), dtype=torch.uint8, device="cuda")
+    lam3 = torch.ones_like(U3d)
+    G3 = torch.empty_like(U3d)
+    reps_saved = reps
+    reps = 5
+    rhs3_ms = timed(lambda: S3.rhs(U3d, alpha_in=a3, out=R3))
+    adj3_ms = timed(lambda: B.teno_rhs_adjoint(g3, U3d, a3, lam3, G3, ws3))
+    reps = reps_saved
+    del ws3, G3, lam3, R3, U3d
+
     tgt, _, _ = rec.forward(torch.from_numpy(Ut.copy()).cuda(), steps, 0.5)
     rho_star = tgt[0].clone()
     torch.cuda.synchronize()
@@ -549,6 +566,8 @@ def adjoint_leg(args, B, W, torch):
         ratios.append(abs(fd - ad) / (1e-6 * max(abs(ad), 0.1 * gmax)))
     fd_s = time.perf_counter() - w0
     worst = max(errs) if errs else None
+    print(f"[bench] adjoint 3D {args.adjoint_n3d}^3: rhs {rhs3_ms:.3f} ms, rhs_adjoint {adj3_ms:.3f} ms",
+          file=sys.stderr, flush=True)
     print(f"[bench] adjoint: rhs {rhs_ms:.4f} ms, rhs_adjoint {adj_ms:.4f} ms; forward {fwd_s:.3f} s, "
           f"backward {bwd_s:.3f} s; FD {len(errs)} cells, max rel {worst}, {skipped} skipped",
           file=sys.stderr, flush=True)
@@ -557,6 +576,9 @@ def adjoint_leg(args, B, W, torch):
                     f"{steps} steps, CFL 0.5, checkpoints every 20 steps",
         "rhs_ms": round(rhs_ms, 5), "rhs_adjoint_ms": round(adj_ms, 5),
         "rhs_adjoint_over_rhs": round(adj_ms / rhs_ms, 3),
+        "rhs_3d": {"workload": f"3D turbulence {args.adjoint_n3d}^3", "rhs_ms": round(rhs3_ms, 4),
+                   "rhs_adjoint_ms": round(adj3_ms, 4),
+                   "rhs_adjoint_over_rhs": round(adj3_ms / rhs3_ms, 3)},
         "forward_recorded_s": round(fwd_s, 4), "backward_s": round(bwd_s, 4),
         "gradient_over_forward": round(bwd_s / fwd_s, 3),
         "fd_check": {"h": h, "cells": len(errs), "skipped_mask_change": skipped,
@@ -736,6 +758,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--table2-steps", type=int, default=10)
+    ap.add_argument("--adjoint-n3d", type=int, default=128)
     ap.add_argument("--fd-cells", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
