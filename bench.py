@@ -807,7 +807,10 @@ def main():
     if not args.no_extras:
         out["schemes"] = schemes_leg(args, B, W, torch)
         out["table2"] = table2_leg(args, B, W, torch)
-        out["batched"] = batched_leg(args, B, W, torch)
+        # the batched kernels are held off the GPU while an unexplained GPU
+        # fault reported during their parity test has no cause
+        out["batched"] = {"skipped": "batched kernels held off the GPU: an unexplained GPU fault "
+                                     "was reported during their parity test"}
         out["adjoint"] = adjoint_leg(args, B, W, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, U)

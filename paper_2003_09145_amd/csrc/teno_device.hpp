@@ -359,6 +359,14 @@ __device__ __forceinline__ int ghost_src(int bc, int n, int j, bool* flip) {
     return j < 0 ? -1 - j : 2 * n - 1 - j;
 }
 
+// Map the hardware block index to a logical index such that blocks that run
+// on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
+// logical indices, so neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 // Local component order of a sweep along DIR: rho, normal momentum, the
 // tangential momenta in increasing axis order, E.
 template <int ND, int DIR>

@@ -55,6 +55,121 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
     ext[(size_t)(2 * NC + 1 + ND) * cap + idx] = H;
 }
 
+// Roe average of the face between stencil cells o + 2 (i) and o + 3 (i+1)
+// and the scalars of its left and right eigenvector matrices (local order:
+// normal velocity un, tangential velocities ut, sound speed cs, ci = 1/cs,
+// b1 = (gamma - 1)/c^2, b2 = b1 |u|^2 / 2).  Shared by the face flux and its
+// adjoint so that both evaluate the same operations.
+template <int ND>
+struct FaceRoe {
+    double rl, rr, wsum;  // sqrt(rho) of cells i, i+1 and 1 / (rl + rr)
+    double ub[ND];        // averaged velocity (natural axes)
+    double Hb, q2, c2, cs, ci, b1, b2, un;
+    double ut[ND > 1 ? ND - 1 : 1];
+    // products shared by the eigenvector entries (each rounded once, as in
+    // the dense oracle matrices)
+    double unci, b1un, unc, hq2;
+    double b1ut[ND > 1 ? ND - 1 : 1];
+};
+
+template <int ND, int DIR>
+__device__ __forceinline__ FaceRoe<ND> face_roe(const double* __restrict__ ext, int cap, int o,
+                                                double gm1) {
+    constexpr int NC = ND + 2;
+    using LO = LocalOrder<ND, DIR>;
+    const double* sr = ext + (size_t)(2 * NC) * cap;
+    const double* uu = ext + (size_t)(2 * NC + 1) * cap;
+    const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
+    FaceRoe<ND> R;
+    R.rl = sr[o + 2];
+    R.rr = sr[o + 3];
+    const double rsum = R.rl + R.rr;
+    R.wsum = cr_div_r(1.0, rsum, rcp_nr(rsum));
+#pragma unroll
+    for (int kk = 0; kk < ND; ++kk)
+        R.ub[kk] = (R.rl * uu[(size_t)kk * cap + o + 2] + R.rr * uu[(size_t)kk * cap + o + 3]) * R.wsum;
+    R.Hb = (R.rl * hh[o + 2] + R.rr * hh[o + 3]) * R.wsum;
+    R.q2 = R.ub[0] * R.ub[0];
+#pragma unroll
+    for (int kk = 1; kk < ND; ++kk) R.q2 = R.q2 + R.ub[kk] * R.ub[kk];
+    R.c2 = gm1 * (R.Hb - 0.5 * R.q2);
+    R.cs = cr_sqrt(R.c2);
+    R.ci = cr_div_r(1.0, R.cs, rcp_nr(R.cs));
+    R.b1 = cr_div_r(gm1, R.c2, rcp_nr(R.c2));
+    R.b2 = (0.5 * R.q2) * R.b1;
+    R.un = R.ub[DIR];
+#pragma unroll
+    for (int kk = 1; kk < ND; ++kk) R.ut[kk - 1] = R.ub[LO::tan_axis(kk)];
+    R.unci = R.un * R.ci;
+    R.b1un = R.b1 * R.un;
+    R.unc = R.un * R.cs;
+    R.hq2 = 0.5 * R.q2;
+#pragma unroll
+    for (int kk = 1; kk < ND; ++kk) R.b1ut[kk - 1] = R.b1 * R.ut[kk - 1];
+    return R;
+}
+
+// Row s of the left eigenvector matrix (local order): acoustic fields s = 0
+// (u - c) and s = NC - 1 (u + c), the entropy field s = 1 and the shear
+// fields s = 2 .. NC - 2, whose row is (-ut, 0, .., 1 at s, .., 0); for them
+// only the first entry is set here and the unit entry is implied.
+template <int ND>
+__device__ __forceinline__ void left_row(const FaceRoe<ND>& R, int s, double (&Lr)[ND + 2]) {
+    constexpr int NC = ND + 2;
+    const bool acoustic = (s == 0 || s == NC - 1);
+    const bool entropy = (s == 1);
+    if (acoustic) {
+        const bool minus = (s == 0);
+        Lr[0] = minus ? 0.5 * (R.b2 + R.unci) : 0.5 * (R.b2 - R.unci);
+        Lr[1] = minus ? 0.5 * (-R.b1un - R.ci) : 0.5 * (-R.b1un + R.ci);
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-R.b1ut[kk - 1]);
+        Lr[NC - 1] = 0.5 * R.b1;
+    } else if (entropy) {
+        Lr[0] = 1.0 - R.b2;
+        Lr[1] = R.b1un;
+#pragma unroll
+        for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = R.b1ut[kk - 1];
+        Lr[NC - 1] = -R.b1;
+    } else {
+        double uts = R.ut[0];
+#pragma unroll
+        for (int kk = 2; kk < ND; ++kk) uts = (s == 1 + kk) ? R.ut[kk - 1] : uts;
+#pragma unroll
+        for (int qq = 0; qq < NC; ++qq) Lr[qq] = 0.0;
+        Lr[0] = -uts;
+    }
+}
+
+// Characteristic field s of the split flux (sg = 0: f+ on cells i-2 .. i+2;
+// sg = 1: f- on the mirrored stencil i+3 .. i-1) projected on the left
+// eigenvector row Lr and reconstructed at the face (eq 2.3-2.15); *code
+// receives the decision code (cutoff mask in bits 5..7).
+template <int ND, bool A5>
+__device__ __forceinline__ double char_rec(const double* __restrict__ ext, int cap, int o, int s,
+                                           int sg, const double (&Lr)[ND + 2],
+                                           const SchemeParams& sch, const DecisionConsts& dk,
+                                           const double* __restrict__ omega, uint32_t* code) {
+    constexpr int NC = ND + 2;
+    const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+    const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
+    double v[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int cj = sg ? 5 - j : j;
+        double acc;
+        if (shear) {
+            acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
+        } else {
+            acc = Lr[0] * fb[cj];
+#pragma unroll
+            for (int qq = 1; qq < NC; ++qq) acc = acc + Lr[qq] * fb[(size_t)qq * cap + cj];
+        }
+        v[j] = acc;
+    }
+    return teno5_rec_fast<A5>(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], code);
+}
+
 // Numerical flux at the face between stencil cells o + 2 and o + 3 (cells
 // i-2 .. i+3 at o .. o + 5): Roe average, left/right eigenvectors, projection
 // of the split fluxes, TENO5-LAD reconstruction of f+ and f- per
@@ -70,40 +185,11 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
                                       double* Fnat, uint32_t* masks = nullptr) {
     constexpr int NC = ND + 2;
     using LO = LocalOrder<ND, DIR>;
-    const double* sr = ext + (size_t)(2 * NC) * cap;
-    const double* uu = ext + (size_t)(2 * NC + 1) * cap;
-    const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
-    // Roe average of cells i (o+2) and i+1 (o+3)
-    const double rl = sr[o + 2], rr = sr[o + 3];
-    const double rsum = rl + rr;
-    const double wsum = cr_div_r(1.0, rsum, rcp_nr(rsum));
-    double ub[ND];
-#pragma unroll
-    for (int kk = 0; kk < ND; ++kk)
-        ub[kk] = (rl * uu[(size_t)kk * cap + o + 2] + rr * uu[(size_t)kk * cap + o + 3]) * wsum;
-    const double Hb = (rl * hh[o + 2] + rr * hh[o + 3]) * wsum;
-    double q2 = ub[0] * ub[0];
-#pragma unroll
-    for (int kk = 1; kk < ND; ++kk) q2 = q2 + ub[kk] * ub[kk];
-    const double c2 = gm1 * (Hb - 0.5 * q2);
-    const double cs = cr_sqrt(c2);
-    const double ci = cr_div_r(1.0, cs, rcp_nr(cs));
-    const double b1 = cr_div_r(gm1, c2, rcp_nr(c2));
-    const double b2 = (0.5 * q2) * b1;
-    const double un = ub[DIR];
-    double ut[ND > 1 ? ND - 1 : 1];
-#pragma unroll
-    for (int kk = 1; kk < ND; ++kk) ut[kk - 1] = ub[LO::tan_axis(kk)];
+    const FaceRoe<ND> R = face_roe<ND, DIR>(ext, cap, o, gm1);
 
     double Fh[NC];  // local order accumulators of R * fhat
 #pragma unroll
     for (int qq = 0; qq < NC; ++qq) Fh[qq] = 0.0;
-    // products shared by the eigenvector entries (each rounded once, as in
-    // the dense oracle matrices)
-    const double unci = un * ci, b1un = b1 * un, unc = un * cs, hq2 = 0.5 * q2;
-    double b1ut[ND > 1 ? ND - 1 : 1];
-#pragma unroll
-    for (int kk = 1; kk < ND; ++kk) b1ut[kk - 1] = b1 * ut[kk - 1];
 
     // Characteristic fields one at a time (s is uniform across the wave, so
     // the field-type branches are scalar): project the split fluxes of the
@@ -113,51 +199,14 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
     for (int s = 0; s < NC; ++s) {
         const bool acoustic = (s == 0 || s == NC - 1);
         const bool entropy = (s == 1);
-        const bool shear = !acoustic && !entropy;
         double Lr[NC];
-        if (acoustic) {
-            const bool minus = (s == 0);
-            Lr[0] = minus ? 0.5 * (b2 + unci) : 0.5 * (b2 - unci);
-            Lr[1] = minus ? 0.5 * (-b1un - ci) : 0.5 * (-b1un + ci);
-#pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = 0.5 * (-b1ut[kk - 1]);
-            Lr[NC - 1] = 0.5 * b1;
-        } else if (entropy) {
-            Lr[0] = 1.0 - b2;
-            Lr[1] = b1un;
-#pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Lr[1 + kk] = b1ut[kk - 1];
-            Lr[NC - 1] = -b1;
-        } else {
-            double uts = ut[0];
-#pragma unroll
-            for (int kk = 2; kk < ND; ++kk) uts = (s == 1 + kk) ? ut[kk - 1] : uts;
-#pragma unroll
-            for (int qq = 0; qq < NC; ++qq) Lr[qq] = 0.0;
-            Lr[0] = -uts;
-        }
+        left_row<ND>(R, s, Lr);
         double fh = 0.0;
 #pragma unroll 1
         for (int sg = 0; sg < 2; ++sg) {
-            // f^+ on cells i-2..i+2, f^- on the mirrored stencil i+3..i-1
             __asm__ __volatile__("" ::: "memory");
-            const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
-            double v[5];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int cj = sg ? 5 - j : j;
-                double acc;
-                if (shear) {
-                    acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
-                } else {
-                    acc = Lr[0] * fb[cj];
-#pragma unroll
-                    for (int qq = 1; qq < NC; ++qq) acc = acc + Lr[qq] * fb[(size_t)qq * cap + cj];
-                }
-                v[j] = acc;
-            }
             uint32_t code;
-            const double r = teno5_rec_fast<A5>(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], &code);
+            const double r = char_rec<ND, A5>(ext, cap, o, s, sg, Lr, sch, dk, omega, &code);
             if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
             if (masks != nullptr) *masks |= (code >> 5) << (3 * (2 * s + sg));
             fh = sg ? fh + r : r;
@@ -166,22 +215,22 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
         if (acoustic) {
             const bool minus = (s == 0);
             Fh[0] = Fh[0] + fh;
-            Fh[1] = Fh[1] + (minus ? (un - cs) : (un + cs)) * fh;
+            Fh[1] = Fh[1] + (minus ? (R.un - R.cs) : (R.un + R.cs)) * fh;
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-            Fh[NC - 1] = Fh[NC - 1] + (minus ? (Hb - unc) : (Hb + unc)) * fh;
+            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + R.ut[kk - 1] * fh;
+            Fh[NC - 1] = Fh[NC - 1] + (minus ? (R.Hb - R.unc) : (R.Hb + R.unc)) * fh;
         } else if (entropy) {
             Fh[0] = Fh[0] + fh;
-            Fh[1] = Fh[1] + un * fh;
+            Fh[1] = Fh[1] + R.un * fh;
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + ut[kk - 1] * fh;
-            Fh[NC - 1] = Fh[NC - 1] + hq2 * fh;
+            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + R.ut[kk - 1] * fh;
+            Fh[NC - 1] = Fh[NC - 1] + R.hq2 * fh;
         } else {
 #pragma unroll
             for (int kk = 1; kk < ND; ++kk) {
                 if (s == 1 + kk) {
                     Fh[1 + kk] = Fh[1 + kk] + fh;
-                    Fh[NC - 1] = Fh[NC - 1] + ut[kk - 1] * fh;
+                    Fh[NC - 1] = Fh[NC - 1] + R.ut[kk - 1] * fh;
                 }
             }
         }

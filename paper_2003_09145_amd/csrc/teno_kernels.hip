@@ -94,14 +94,6 @@ __device__ __forceinline__ int boundary_kind(const teno_boundary* bnd, const ten
     return kind;
 }
 
-// Map the hardware block index to a logical index such that blocks that run
-// on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
-// logical indices, so neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
-    const int64_t q = G / 8, r = G % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
-
 // 64-bit mixer (the splitmix64 finaliser) for the cutoff-mask digest.
 __device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
     z += 0x9e3779b97f4a7c15ull;

@@ -76,6 +76,17 @@ def test_rhs_adjoint_full_jacobian(torch, B, orc, name):
     ("2d_random40x33", lambda: (lambda p: (p, W.random_field(p, seed=31)))(
         W.uniform_problem(2, [40, 33], [0.0, 0.0], [1.0, 1.0], ["transmissive", "reflective"]))),
     ("3d_turbulence12", lambda: W.turbulence_3d(12)),
+    # lines longer than one 64-face chunk and chunks that wrap between lines
+    # on every axis, each boundary kind on each axis
+    ("3d_random70x66x9_mixed", lambda: (lambda p: (p, W.random_field(p, seed=32)))(
+        W.uniform_problem(3, [70, 66, 9], [0.0] * 3, [1.0] * 3,
+                          ["periodic", "reflective", "transmissive"]))),
+    ("3d_random9x5x131_mixed", lambda: (lambda p: (p, W.random_field(p, seed=33)))(
+        W.uniform_problem(3, [9, 5, 131], [0.0] * 3, [1.0] * 3,
+                          ["reflective", "transmissive", "periodic"]))),
+    ("2d_teno5a_130x67", lambda: (lambda p: (p, W.random_field(p, seed=34)))(
+        W.uniform_problem(2, [130, 67], [0.0, 0.0], [1.0, 1.0], ["transmissive", "periodic"],
+                          scheme="teno5a"))),
 ])
 def test_rhs_adjoint_dot_product(torch, B, orc, name, mk):
     prob, U = mk()
