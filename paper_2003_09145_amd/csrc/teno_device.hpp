@@ -68,22 +68,26 @@ __device__ __forceinline__ bool in_safe_range(double v) {
 }
 
 // Sufficient test that q = RN(a / b) given r = RN(a - q b): |a/b - q| <
-// ulp(q)/2 with both neighbours of q one ulp away (q not a power of two)
-// makes q the nearest double.  The bound ulp(q)/2 |b| = |b| 2^(e(q) - 54) is
-// exact (a power-of-two scaling that stays normal for operands in the safe
-// range), and rounding is monotone, so |r| below it implies the exact
-// remainder is below it as well, whether or not r itself is exact.
+// ulp(q)/2 with both neighbours of q one ulp away makes q the nearest
+// double.  q = mq 2^eq with |mq| in (1/2, 1) excludes zero, powers of two,
+// infinities and NaN; ulp(q)/2 |b| = |b| 2^(eq - 54) is computed exactly when
+// it is a normal number (checked; for a subnormal q the bound is smaller than
+// the true half-ulp, which only makes the test stricter); and rounding is
+// monotone, so |r| below the bound implies the exact remainder is below it,
+// whether or not r itself is exact.  Signed zeros and operands outside the
+// normal range therefore never pass and take the exact path.
 __device__ __forceinline__ bool quotient_is_nearest(double q, double b, double r) {
     int eq;
-    const double mq = frexp(q, &eq);  // q = mq 2^eq, |mq| in [1/2, 1), ulp(q) = 2^(eq - 53)
-    return fabs(r) < ldexp(fabs(b), eq - 54) && fabs(mq) != 0.5;
+    const double mq = frexp(q, &eq);
+    const double hb = ldexp(fabs(b), eq - 54);
+    return fabs(r) < hb && hb >= 0x1p-1000 && fabs(mq) > 0.5;
 }
 
 __device__ __forceinline__ double cr_div(double a, double b) {
     const double q = a / b;
-    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return q;
-    const double r = __builtin_fma(-q, b, a);  // a - q b, exact
+    const double r = __builtin_fma(-q, b, a);  // a - q b, exact in the safe range
     if (quotient_is_nearest(q, b, r)) return q;
+    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return q;
     if (r == 0.0) return q;
     const bool up = (r > 0.0) == (b > 0.0);     // true quotient above q
     const double qn = step_toward(q, up);
@@ -122,9 +126,9 @@ __device__ __forceinline__ double cr_div_r(double a, double b, double rb) {
     const double q0 = a * rb;
     const double e = __builtin_fma(-q0, b, a);
     const double q = __builtin_fma(e, rb, q0);
-    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return cr_div(a, b);
-    const double r = __builtin_fma(-q, b, a);  // exact
+    const double r = __builtin_fma(-q, b, a);  // exact in the safe range
     if (quotient_is_nearest(q, b, r)) return q;
+    if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return cr_div(a, b);
     if (r == 0.0) return q;
     const bool up = (r > 0.0) == (b > 0.0);
     const double qn = step_toward(q, up);
