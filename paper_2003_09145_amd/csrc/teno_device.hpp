@@ -98,7 +98,7 @@ __device__ __forceinline__ double cr_div(double a, double b) {
     return q;
 }
 
-__device__ __forceinline__ double cr_sqrt(double x) {
+__device__ __forceinline__ double cr_sqrt_exact(double x) {
     const double s = sqrt(x);
     if (!(x >= 0x1p-900 && x <= 0x1p900)) return s;
     const double r = __builtin_fma(-s, s, x);  // x - s^2, exact
@@ -108,6 +108,35 @@ __device__ __forceinline__ double cr_sqrt(double x) {
     const double sg = s * (sn - s);             // exact: the gap is a power of two
     if (up) return (r > sg) ? sn : s;
     return (r <= sg) ? sn : s;
+}
+
+// sqrt(x) correctly rounded.  In the safe range the root comes from the
+// hardware reciprocal square root refined by one Goldschmidt and two Newton
+// steps (no scaling is needed there) and is accepted when
+// |x - s^2| < ulp(s) (s - ulp(s)): a root error of half an ulp or more would
+// make |x - s^2| >= ulp(s) (s - ulp(s)/4), and rounding is monotone, so the
+// accepted s is the nearest double (s not a power of two, both neighbours one
+// ulp away; the bound is exact and normal).  Everything else takes the exact
+// neighbour test on the compiler's root.
+__device__ __forceinline__ double cr_sqrt(double x) {
+    if (x >= 0x1p-900 && x <= 0x1p900) {
+        const double y = __builtin_amdgcn_rsq(x);
+        double s = x * y;
+        double h = 0.5 * y;
+        const double e = __builtin_fma(-h, s, 0.5);
+        s = __builtin_fma(s, e, s);
+        h = __builtin_fma(h, e, h);
+        double d = __builtin_fma(-s, s, x);
+        s = __builtin_fma(d, h, s);
+        d = __builtin_fma(-s, s, x);
+        s = __builtin_fma(d, h, s);
+        const double r = __builtin_fma(-s, s, x);
+        int es;
+        const double ms = frexp(s, &es);
+        const double u = ldexp(1.0, es - 53);                 // ulp(s)
+        if (fabs(r) < ldexp(s - u, es - 53) && ms > 0.5) return s;
+    }
+    return cr_sqrt_exact(x);
 }
 
 // Reciprocal to within a few ulp: hardware estimate plus two Newton steps.
