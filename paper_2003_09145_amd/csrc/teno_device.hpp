@@ -406,6 +406,11 @@ __device__ __forceinline__ int ghost_src(int bc, int n, int j, bool* flip) {
     return j < 0 ? -1 - j : 2 * n - 1 - j;
 }
 
+// floor(x / d) for 0 <= x < 2^31 from the host's DivMagic constants of d.
+__device__ __forceinline__ int div_by(int x, uint32_t m, uint32_t sh) {
+    return (int)(((uint64_t)(uint32_t)x * m) >> sh);
+}
+
 // Map the hardware block index to a logical index such that blocks that run
 // on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
 // logical indices, so neighbouring tiles share that XCD's L2.

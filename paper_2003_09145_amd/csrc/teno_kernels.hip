@@ -63,6 +63,10 @@ struct SweepArgs {
     int32_t add_source;        // 1 on the last axis when bnd is set
     int32_t nx, ny;            // grid sizes (boundary split coordinates)
     double dxa[3];             // spacings per axis (boundary split coordinates)
+    // multiply-and-shift division by n + 1, n + 6 and ncols (dividends < 2^31);
+    // div32: every face and ext index of a column is below 2^31
+    uint32_t m1, s1, m6, s6, mc, sc;
+    int32_t div32;
 };
 
 // Boundary kind of the ghost cells at end `end` of axis `dir` for the line
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (A.ctrl != nullptr) {
         if (!A.ctrl->active || A.ctrl->status != 0) return;  // uniform across the grid
     }
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int64_t chunk = lb * W + wave;
@@ -124,8 +128,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t np1 = n + 1, np6 = n + 6;
     int64_t col = 0, k = chunk;
     if (DIR != 0) {  // columns fastest: neighbouring waves read neighbouring x
-        col = chunk % A.ncols;
-        k = chunk / A.ncols;
+        k = div_by((int)chunk, A.mc, A.sc);  // chunk < nchunks < 2^31
+        col = chunk - k * A.ncols;
     }
     const int64_t colbase = col * A.col_step;
     const int cap = CAPC ? CAPC : A.ext_cap;
@@ -144,22 +148,24 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t Fc = valid ? F : F0;
     // line and in-line index of this lane's face, from those of F0 (uniform)
     // with a 32-bit step
-    const int64_t bl0 = F0 / np1;
+    const int64_t bl0 = A.div32 ? (int64_t)div_by((int)F0, A.m1, A.s1) : F0 / np1;
     const int phi0 = (int)(F0 - bl0 * np1);
     const int tq = phi0 + (int)(Fc - F0);
-    const int wraps = tq / (int)np1;
+    const int wraps = div_by(tq, A.m1, A.s1);
     const int64_t bl = bl0 + wraps;                        // line of this lane's face
     const int64_t phi = tq - wraps * (int)np1;             // face index in the line (i + 1)
     const int64_t e_lo = F0 + 5 * bl0;
     int64_t Flast = F0 + 63;
     if (Flast > A.ftot - 1) Flast = A.ftot - 1;
-    const int64_t e_hi = Flast + 5 * (Flast / np1) + 6;
+    const int64_t e_hi =
+        Flast + 5 * (A.div32 ? (int64_t)div_by((int)Flast, A.m1, A.s1) : Flast / np1) + 6;
     const int count = wave_ok ? (int)(e_hi - e_lo) : 0;
 
     // ---- stage per-cell quantities of the ext cells [e_lo, e_hi) ----------
     const double alpha = A.alpha[DIR];
     const double gm1 = A.sch.gamma - 1.0;
-    const int64_t be0 = e_lo / np6;                 // line of the first ext cell (uniform)
+    const int64_t be0 = A.div32 ? (int64_t)div_by((int)e_lo, A.m6, A.s6)
+                                : e_lo / np6;       // line of the first ext cell (uniform)
     const int je0 = (int)(e_lo - be0 * np6);
     // COOP (y and z sweeps, W waves = W neighbouring columns of one line chunk,
     // which the host guarantees): thread t stages column t % W, so a wave's
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     double* ext_c = smem + 24 + (size_t)cc * per_wave;
     for (int idx = COOP ? (int)(threadIdx.x / W) : lane; idx < count; idx += 64) {
         const int jq = je0 + idx;
-        const int bw = jq / (int)np6;
+        const int bw = div_by(jq, A.m6, A.s6);
         const int64_t b = be0 + bw;
         const int j = jq - bw * (int)np6 - 3;
         bool flip = false;
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     if constexpr (COOP) {
         jj = (int)(threadIdx.x / W);
         const int tqj = phi0 + jj;
-        const int wrj = tqj / (int)np1;
+        const int wrj = div_by(tqj, A.m1, A.s1);
         blj = bl0 + wrj;
         phij = tqj - wrj * (int)np1;
         upd = F0 + jj < A.ftot && jj > 0 && phij > 0;
@@ -605,6 +611,12 @@ static hipError_t launch_sweep(const teno_grid* g, int dir, SweepArgs A, hipStre
     A.ftot = lines_per_col * (n + 1);
     const int64_t chunks_per_col = (A.ftot - 1 + kCellsPerChunk - 1) / kCellsPerChunk;
     A.nchunks = chunks_per_col * A.ncols;
+    if (A.nchunks > (int64_t(1) << 31) - 64) return hipErrorInvalidValue;  // chunk indices are 32-bit
+    const DivMagic d1 = div_magic((uint32_t)(n + 1)), d6 = div_magic((uint32_t)(n + 6)),
+                   dc = div_magic((uint32_t)A.ncols);
+    A.m1 = d1.m; A.s1 = d1.sh; A.m6 = d6.m; A.s6 = d6.sh; A.mc = dc.m; A.sc = dc.sh;
+    // largest ext index of a column: ftot + 5 lines_per_col (+ the chunk's tail)
+    A.div32 = (A.ftot + 6 * lines_per_col + 128) < (int64_t(1) << 31) ? 1 : 0;
     const bool digest = A.digest != nullptr && (g->flags & TENO_FLAG_MASK_DIGEST) != 0;
     const int key = g->ndim * 4 + dir + (g->scheme == TENO_SCHEME_TENO5A ? 16 : 0);
     switch (key) {
