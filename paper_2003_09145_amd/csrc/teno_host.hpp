@@ -10,6 +10,7 @@
 
 #include "../../include/teno.h"
 #include "teno_device.hpp"
+#include "teno_divmagic.hpp"
 
 namespace teno {
 
@@ -60,18 +61,6 @@ inline SchemeParams scheme_of(const teno_grid* g) {
         s.epsA = ((0.9 * g->cr) / (1.0 - 0.9 * g->cr)) * (g->xi * g->xi);  // eq 2.18
     }
     return s;
-}
-
-// Division by an invariant d >= 1 as a multiply and shift (Granlund and
-// Montgomery): with l = ceil(log2 d) and m = ceil(2^(31 + l) / d) < 2^32,
-// floor(x / d) = (x m) >> (31 + l) for every 0 <= x < 2^31.
-struct DivMagic {
-    uint32_t m, sh;
-};
-inline DivMagic div_magic(uint32_t d) {
-    int l = 0;
-    while ((1ull << l) < d) ++l;
-    return {(uint32_t)(((1ull << (31 + l)) + d - 1) / d), (uint32_t)(31 + l)};
 }
 
 inline int ext_cap_for(int n) { return 69 + 5 * (63 / (n + 1) + 1); }
