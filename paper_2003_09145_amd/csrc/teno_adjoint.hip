@@ -62,6 +62,12 @@ struct AdjArgs {
     int64_t ncell, line_step, stride, col_step, ftot, ncols;
     int64_t kchunks;      // chunks per column
     int32_t n, bc, accumulate, cap;
+    // multiply-and-shift division by n + 1, n + 6, ncols, n and the line count
+    // of a DIR-2 column (dividends < 2^31); div32: every cell, face and ext
+    // index is below 2^31
+    uint32_t m1, s1, m6, s6, mc, sc, mn, sn, mb, sb;
+    int32_t div32;
+    int32_t nb;  // lines of a DIR-2 column (ny)
     double dx;
     SchemeParams sch;
     DecisionConsts dk;
@@ -73,7 +79,7 @@ struct AdjArgs {
 __device__ __forceinline__ int64_t ext_source(const AdjArgs& A, int64_t colbase, int64_t be0,
                                               int jq, bool* flip) {
     const int np6 = A.n + 6;
-    const int bw = jq / np6;
+    const int bw = div_by(jq, A.m6, A.s6);
     const int j = jq - bw * np6 - 3;
     const int src = ghost_src(A.bc, A.n, j, flip);
     return colbase + (be0 + bw) * A.line_step + (int64_t)src * A.stride;
@@ -98,8 +104,8 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     const int64_t chunk = xcd_logical_block(blockIdx.x, gridDim.x);
     int64_t col = 0, k = chunk;
     if (DIR != 0) {  // columns fastest, as in the forward sweep
-        col = chunk % A.ncols;
-        k = chunk / A.ncols;
+        k = div_by((int)chunk, A.mc, A.sc);  // chunk < kchunks ncols < 2^31
+        col = chunk - k * A.ncols;
     }
     const int n = A.n;
     const int64_t np1 = n + 1, np6 = n + 6;
@@ -108,17 +114,18 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     const int64_t F = F0 + lane;
     const bool valid = F < A.ftot;
     const int64_t Fc = valid ? F : F0;
-    const int64_t bl0 = F0 / np1;
+    const int64_t bl0 = A.div32 ? (int64_t)div_by((int)F0, A.m1, A.s1) : F0 / np1;
     const int phi0 = (int)(F0 - bl0 * np1);
     const int tq = phi0 + (int)(Fc - F0);
-    const int wraps = tq / (int)np1;
+    const int wraps = div_by(tq, A.m1, A.s1);
     const int64_t bl = bl0 + wraps;             // line of this lane's face
     const int phi = tq - wraps * (int)np1;      // face index in the line
     const int64_t e_lo = F0 + 5 * bl0;
     int64_t Flast = F0 + kAdjChunk - 1;
     if (Flast > A.ftot - 1) Flast = A.ftot - 1;
-    const int count = (int)(Flast + 5 * (Flast / np1) + 6 - e_lo);
-    const int64_t be0 = e_lo / np6;
+    const int count = (int)(Flast + 5 * (A.div32 ? (int64_t)div_by((int)Flast, A.m1, A.s1)
+                                                  : Flast / np1) + 6 - e_lo);
+    const int64_t be0 = A.div32 ? (int64_t)div_by((int)e_lo, A.m6, A.s6) : e_lo / np6;
     const int je0 = (int)(e_lo - be0 * np6);
     const double alpha = A.alpha[DIR];
     const double gm1 = A.sch.gamma - 1.0;
@@ -404,17 +411,35 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjArgs A) {
     // (column, line, position) of the cell along DIR
     int64_t col, b;
     int i;
-    if (DIR == 0) {
+    if (A.div32) {
+        if (DIR == 0) {
+            col = 0;
+            b = div_by((int)cell, A.mn, A.sn);
+            i = (int)(cell - b * A.n);
+        } else {
+            const int64_t rest = div_by((int)cell, A.mc, A.sc);  // (z, y) for DIR 1: y fastest
+            col = cell - rest * A.ncols;
+            const int64_t hi = div_by((int)rest, DIR == 1 ? A.mn : A.mb, DIR == 1 ? A.sn : A.sb);
+            const int64_t lo = rest - hi * (DIR == 1 ? A.n : A.nb);
+            if (DIR == 1) {
+                i = (int)lo;
+                b = hi;
+            } else {  // DIR 2: rest = z ny + y, lines ordered by y
+                b = lo;
+                i = (int)hi;
+            }
+        }
+    } else if (DIR == 0) {
         col = 0;
         b = cell / A.n;
         i = (int)(cell - b * A.n);
     } else {
         col = cell % A.ncols;
-        const int64_t rest = cell / A.ncols;  // (z, y) for DIR 1: y fastest
+        const int64_t rest = cell / A.ncols;
         if (DIR == 1) {
             i = (int)(rest % A.n);
             b = rest / A.n;
-        } else {  // DIR 2: rest = z ny + y, lines ordered by y
+        } else {
             const int64_t ny = A.stride / A.ncols;
             b = rest % ny;
             i = (int)(rest / ny);
@@ -448,7 +473,8 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjArgs A) {
         const int64_t ka = Fa / kAdjChunk, kz = Fz / kAdjChunk;
         for (int64_t kk = ka; kk <= kz; ++kk) {
             const int64_t F0 = kk * kAdjChunk;
-            const int64_t slot = E - (F0 + 5 * (F0 / np1));
+            const int64_t slot =
+                E - (F0 + 5 * (A.div32 ? (int64_t)div_by((int)F0, A.m1, A.s1) : F0 / np1));
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[c] += A.P[((kk * NC + c) * A.cap + slot) * A.ncols + col];
         }
@@ -559,6 +585,17 @@ static hipError_t rhs_adjoint_impl(const teno_grid* g, const double* U, const do
         A.stride = X.stride;
         A.ftot = X.ftot;
         A.kchunks = X.kchunks;
+        if (A.kchunks * A.ncols > (int64_t(1) << 31) - 64) return hipErrorInvalidValue;
+        const int64_t nb = (d == 2) ? A.stride / A.ncols : 1;  // lines of a DIR-2 column
+        const DivMagic d1 = div_magic((uint32_t)(A.n + 1)), d6 = div_magic((uint32_t)(A.n + 6)),
+                       dc = div_magic((uint32_t)A.ncols), dn = div_magic((uint32_t)A.n),
+                       db = div_magic((uint32_t)nb);
+        A.m1 = d1.m; A.s1 = d1.sh; A.m6 = d6.m; A.s6 = d6.sh; A.mc = dc.m; A.sc = dc.sh;
+        A.mn = dn.m; A.sn = dn.sh; A.mb = db.m; A.sb = db.sh;
+        A.nb = (int32_t)nb;
+        // largest index: a cell, or an ext index ftot + 5 lines (+ a chunk's tail)
+        const int64_t lines = A.ftot / (A.n + 1);
+        A.div32 = (A.ncell < (int64_t(1) << 31) && A.ftot + 6 * lines + 128 < (int64_t(1) << 31)) ? 1 : 0;
         hipError_t e = hipErrorInvalidValue;
         switch (g->ndim * 4 + d) {
             case 4: e = launch_adj<1, 0>(A, st); break;
