@@ -119,7 +119,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (A.ctrl != nullptr) {
         if (!A.ctrl->active || A.ctrl->status != 0) return;  // uniform across the grid
     }
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the wave index is uniform; saying so explicitly keeps the y and z
+    // variants' column split scalar (along x it only costs registers)
+    const int wave = DIR != 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int64_t chunk = lb * W + wave;
