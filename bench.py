@@ -746,6 +746,53 @@ def summarize_counters(d):
     print("\n".join(lines))
 
 
+TRACE_FILE = os.path.join(ROOT, "profiles", "k_sweep_3d_256_kernel_trace.txt")
+
+
+def summarize_trace(d, bench_json=None):
+    """profiles/k_sweep_3d_256_kernel_trace.txt from a rocprofv3 --kernel-trace
+    --stats run of the headline (DIR/trace/*kernel_stats.csv) and, if given,
+    the JSON line of a default bench.py run (its HIP-event sweep averages)."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "trace", "*kernel_stats.csv"))
+    if not path:
+        raise SystemExit(f"no kernel_stats.csv under {d}/trace")
+    rows = list(csv.DictReader(open(path[0])))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [
+        "# rocprofv3 kernel-trace summary: 3D periodic turbulence 256^3, TENO5-LAD, SSP-RK3",
+        "#",
+        "# command (repository root, after cd /tmp && export TMPDIR=/tmp; $OUT is any output "
+        "directory):",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o trace -- "
+        "python3 bench.py --no-cpu-baseline --no-extras",
+        "#   python3 bench.py --summarize-trace $OUT [bench.json of a default run]",
+        "# (the headline of the default bench.py run: 3 warm-up + 100 timed steps, 3 stages each,",
+        "#  so 309 launches of each per-stage kernel)",
+        f"source_sha256: {sources_sha()}",
+        "#",
+        f"{'kernel':58s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+        f"{'share_%':>8s}",
+    ]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].replace("void ", "").replace("teno::", "").split("(")[0]
+        lines.append(f"{name[:58]:58s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                     f"{100.0 * float(r['TotalDurationNs']) / total:8.2f}")
+    if bench_json:
+        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        sw = b["roofline"]["sweep_ms_xyz"]
+        lines += ["#",
+                  "# same kernels timed inside bench.py's timed region with HIP events around each",
+                  "# launch (teno_step_timed, default run: 100 steps, inputs resident in HBM):",
+                  f"#   sweep x / y / z average launch: {sw[0] * 1e3:.1f} / {sw[1] * 1e3:.1f} / "
+                  f"{sw[2] * 1e3:.1f} us; ms per RK3 step {b['ms_per_step']:.3f}"]
+    with open(TRACE_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -765,9 +812,13 @@ def main():
                     help="headline only (no schemes / batched / adjoint legs)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
+    ap.add_argument("--summarize-trace", nargs="+", metavar=("DIR", "BENCH_JSON"))
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace[:2])
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (--gpus 1); sharding over several "
