@@ -56,7 +56,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_3d_256_traffic.txt")
 SWEEP_SOURCES = ["paper_2003_09145_amd/csrc/teno_kernels.hip",
                  "paper_2003_09145_amd/csrc/teno_face.hpp",
                  "paper_2003_09145_amd/csrc/teno_device.hpp",
-                 "paper_2003_09145_amd/csrc/teno_host.hpp", "include/teno.h"]
+                 "paper_2003_09145_amd/csrc/teno_host.hpp",
+                 "paper_2003_09145_amd/csrc/teno_divmagic.hpp", "include/teno.h"]
 COPY_BYTES = 1 << 30
 
 
