@@ -12,9 +12,10 @@
  * benchmark load this library.  The product path never does, and this file
  * shares no code, header or table with it.
  *
- * Build: g++ -O2 -ffp-contract=off -fopenmp (never -ffast-math), so every
+ * Build: g++ -O2 -ffp-contract=off -mfma -fopenmp (never -ffast-math), so every
  * + - * / sqrt below is exactly one IEEE-754 binary64 operation, evaluated in
- * the order written (left to right unless parenthesised).
+ * the order written (left to right unless parenthesised), and every fmadd is
+ * one correctly rounded fused multiply-add (std::fma).
  *
  * The scalar type is a template parameter so that a forward-mode dual number
  * can run through the same code (Jacobian-vector products for the adjoint
@@ -35,7 +36,11 @@
  *    that may move in time (evaluated at the stage times t, t + dt,
  *    t + dt/2);
  *  - the gravity source of the Rayleigh-Taylor problem is added after the
- *    flux differences.
+ *    flux differences;
+ *  - the sums of products of the reconstruction (smoothness indicators
+ *    eq 2.9-2.11, candidate fluxes eq 2.4-2.6, their weighted sum eq 2.7) and
+ *    of the characteristic projection onto the left eigenvectors are
+ *    evaluated with fused multiply-adds, in the order written below.
  */
 #include <cmath>
 #include <cstdint>
@@ -105,6 +110,12 @@ inline Dual dsqrt(Dual a) {
     return {s, a.d / (2.0 * s)};
 }
 inline double dsqrt(double a) { return std::sqrt(a); }
+/* a b + c with one rounding of the value; tangents by the product rule */
+inline double fmadd(double a, double b, double c) { return std::fma(a, b, c); }
+inline Dual fmadd(Dual a, Dual b, Dual c) {
+    return {std::fma(a.v, b.v, c.v), (a.d * b.v + a.v * b.d) + c.d};
+}
+inline Dual fmadd(double a, Dual b, Dual c) { return {std::fma(a, b.v, c.v), a * b.d + c.d}; }
 inline double val(double x) { return x; }
 inline double val(Dual x) { return x.v; }
 template <class T> inline T from_double(double x);
@@ -150,15 +161,15 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
     /* Jiang-Shu smoothness indicators, eq 2.9-2.11, on (f_{i-2} .. f_{i+2}) =
      * (a, b, c, d, e). */
     double s01 = (a - 2.0 * b) + c;
-    double s02 = (a - 4.0 * b) + 3.0 * c;
+    double s02 = fmadd(3.0, c, a - 4.0 * b);
     double s11 = (b - 2.0 * c) + d;
     double s12 = b - d;
     double s21 = (c - 2.0 * d) + e;
-    double s22 = (3.0 * c - 4.0 * d) + e;
+    double s22 = fmadd(3.0, c, e - 4.0 * d);
     double beta[3];
-    beta[0] = K13_12 * (s01 * s01) + K1_4 * (s02 * s02);
-    beta[1] = K13_12 * (s11 * s11) + K1_4 * (s12 * s12);
-    beta[2] = K13_12 * (s21 * s21) + K1_4 * (s22 * s22);
+    beta[0] = fmadd(K13_12 * s01, s01, K1_4 * (s02 * s02));
+    beta[1] = fmadd(K13_12 * s11, s11, K1_4 * (s12 * s12));
+    beta[2] = fmadd(K13_12 * s21, s21, K1_4 * (s22 * s22));
     /* Global smoothness indicator tau_5 = |beta_2 - beta_0|, eq 2.12. */
     double tau = std::fabs(beta[2] - beta[0]);
     /* chi-tilde_k = tau / (beta_k + eps) (eq 3.2), which is also the ratio
@@ -254,15 +265,15 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
  * eq 2.15, combination eq 2.7.  Linear in (a..e) once the mask is fixed. */
 template <class T>
 T teno_flux(int mask, T a, T b, T c, T d, T e) {
-    T f0 = (T1_3 * a - T7_6 * b) + T11_6 * c;
-    T f1 = (-T1_6 * b + T5_6 * c) + T1_3 * d;
-    T f2 = (T1_3 * c + T5_6 * d) - T1_6 * e;
+    T f0 = fmadd(T11_6, c, fmadd(T1_3, a, -T7_6 * b));
+    T f1 = fmadd(T1_3, d, fmadd(-T1_6, b, T5_6 * c));
+    T f2 = fmadd(-T1_6, e, fmadd(T1_3, c, T5_6 * d));
     double dl[3];
     for (int k = 0; k < 3; ++k) dl[k] = (double)((mask >> k) & 1);
     double D = (dl[0] * C_LIN[0] + dl[1] * C_LIN[1]) + dl[2] * C_LIN[2];
     double w[3];
     for (int k = 0; k < 3; ++k) w[k] = (dl[k] * C_LIN[k]) / D;
-    return (w[0] * f0 + w[1] * f1) + w[2] * f2;
+    return fmadd(w[2], f2, fmadd(w[0], f0, w[1] * f1));
 }
 
 template <class T>
@@ -496,8 +507,8 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
             T ap = Lm[s][0] * fp[j][0];
             T am = Lm[s][0] * fm[j][0];
             for (int q = 1; q < nc; ++q) {
-                ap = ap + Lm[s][q] * fp[j][q];
-                am = am + Lm[s][q] * fm[j][q];
+                ap = fmadd(Lm[s][q], fp[j][q], ap);
+                am = fmadd(Lm[s][q], fm[j][q], am);
             }
             vp[j] = ap;
             vm[j] = am;

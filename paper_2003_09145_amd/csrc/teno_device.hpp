@@ -305,15 +305,16 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
                                                  const double* __restrict__ omega_lds,
                                                  double a, double b, double c, double d,
                                                  double e, uint32_t* code) {
+    // sums of products as fused multiply-adds, in the oracle's order
     const double s01 = (a - 2.0 * b) + c;
-    const double s02 = (a - 4.0 * b) + 3.0 * c;
+    const double s02 = __builtin_fma(3.0, c, a - 4.0 * b);
     const double s11 = (b - 2.0 * c) + d;
     const double s12 = b - d;
     const double s21 = (c - 2.0 * d) + e;
-    const double s22 = (3.0 * c - 4.0 * d) + e;
-    const double beta0 = kB13_12 * (s01 * s01) + kB1_4 * (s02 * s02);
-    const double beta1 = kB13_12 * (s11 * s11) + kB1_4 * (s12 * s12);
-    const double beta2 = kB13_12 * (s21 * s21) + kB1_4 * (s22 * s22);
+    const double s22 = __builtin_fma(3.0, c, e - 4.0 * d);
+    const double beta0 = __builtin_fma(kB13_12 * s01, s01, kB1_4 * (s02 * s02));
+    const double beta1 = __builtin_fma(kB13_12 * s11, s11, kB1_4 * (s12 * s12));
+    const double beta2 = __builtin_fma(kB13_12 * s21, s21, kB1_4 * (s22 * s22));
 
     uint32_t cd;
     if (S.scheme == 2) {
@@ -388,11 +389,11 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
     }
     *code = cd;
     const uint32_t mask = cd >> 5;
-    const double f0 = (kC1_3 * a - kC7_6 * b) + kC11_6 * c;
-    const double f1 = (-kC1_6 * b + kC5_6 * c) + kC1_3 * d;
-    const double f2 = (kC1_3 * c + kC5_6 * d) - kC1_6 * e;
+    const double f0 = __builtin_fma(kC11_6, c, __builtin_fma(kC1_3, a, -kC7_6 * b));
+    const double f1 = __builtin_fma(kC1_3, d, __builtin_fma(-kC1_6, b, kC5_6 * c));
+    const double f2 = __builtin_fma(-kC1_6, e, __builtin_fma(kC1_3, c, kC5_6 * d));
     const double* w = omega_lds + 3 * mask;
-    return (w[0] * f0 + w[1] * f1) + w[2] * f2;
+    return __builtin_fma(w[2], f2, __builtin_fma(w[0], f0, w[1] * f1));
 }
 
 // Ghost-cell source along a swept axis: periodic wrap, zero-gradient copy or

@@ -158,12 +158,13 @@ __device__ __forceinline__ double char_rec(const double* __restrict__ ext, int c
     for (int j = 0; j < 5; ++j) {
         const int cj = sg ? 5 - j : j;
         double acc;
-        if (shear) {
+        if (shear) {  // the unit entry: a plain add, as the oracle's fma by 1
             acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
         } else {
             acc = Lr[0] * fb[cj];
 #pragma unroll
-            for (int qq = 1; qq < NC; ++qq) acc = acc + Lr[qq] * fb[(size_t)qq * cap + cj];
+            for (int qq = 1; qq < NC; ++qq)
+                acc = __builtin_fma(Lr[qq], fb[(size_t)qq * cap + cj], acc);
         }
         v[j] = acc;
     }

@@ -310,13 +310,34 @@ def _sampled(torch, B, orc, prob, U, nsample, seed):
     return flips, rel, np.array_equal(Rg, Rc), tot, out
 
 
+def _flux_scale(prob, U):
+    """Sum over cells and axes of 2 |F_d| / dx_d per component (cell-centre
+    Euler fluxes as the magnitude of the face fluxes)."""
+    nd, g = prob.ndim, prob.gamma
+    rho, m, E = U[0], U[1:1 + nd], U[nd + 1]
+    u = m / rho
+    p = (g - 1.0) * (E - 0.5 * np.sum(m * u, axis=0))
+    S = np.zeros(nd + 2)
+    for d in range(nd):
+        S[0] += 2.0 * np.abs(m[d]).sum() / prob.dx[d]
+        for k in range(nd):
+            S[1 + k] += 2.0 * np.abs(m[k] * u[d] + (p if k == d else 0.0)).sum() / prob.dx[d]
+        S[nd + 1] += 2.0 * np.abs((E + p) * u[d]).sum() / prob.dx[d]
+    return S
+
+
 def test_full_size_3d_256_sampled(torch, B, orc):
     prob, U = W.turbulence_3d(256)
     flips, rel, bitwise, tot, out = _sampled(torch, B, orc, prob, U, 1500, 100)
     assert flips == 0 and rel <= REL and bitwise
-    # periodic: the RHS sums to zero up to round-off (telescoping eq 2.2)
-    mag = out.abs().reshape(5, -1).sum(dim=1).cpu().numpy()
-    assert np.all(np.abs(tot) <= 1e-12 * mag)
+    # periodic: the RHS sums to zero up to round-off (eq 2.2 telescopes
+    # exactly, each face flux being shared by its two cells).  The rounding
+    # left is that of each cell's flux difference, division by dx and
+    # accumulation over the axes, relative to the per-axis flux terms -- which
+    # for this nearly divergence-free field are far larger than the RHS itself
+    bound = 8.0 * np.finfo(np.float64).eps * _flux_scale(prob, U)
+    print(f"[sampled parity] RHS sums {tot} vs rounding bound {bound}", flush=True)
+    assert np.all(np.abs(tot) <= bound)
 
 
 def test_full_size_2d_2048_sampled(torch, B, orc):
