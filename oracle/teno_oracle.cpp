@@ -38,9 +38,11 @@
  *  - the gravity source of the Rayleigh-Taylor problem is added after the
  *    flux differences;
  *  - the sums of products of the reconstruction (smoothness indicators
- *    eq 2.9-2.11, candidate fluxes eq 2.4-2.6, their weighted sum eq 2.7) and
- *    of the characteristic projection onto the left eigenvectors are
- *    evaluated with fused multiply-adds, in the order written below.
+ *    eq 2.9-2.11, candidate fluxes eq 2.4-2.6, their weighted sum eq 2.7),
+ *    of the global Lax-Friedrichs split (F +- alpha U) / 2, of the
+ *    characteristic projection onto the left eigenvectors and of the
+ *    back-projection R f^ are evaluated with fused multiply-adds, in the
+ *    order written below.
  */
 #include <cmath>
 #include <cstdint>
@@ -493,8 +495,8 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
         euler_flux(P, d, st[j], w, F);
         for (int q = 0; q < nc; ++q) {
             int g = perm[q];
-            fp[j][q] = 0.5 * (F[g] + alpha * st[j][g]);
-            fm[j][q] = 0.5 * (F[g] - alpha * st[j][g]);
+            fp[j][q] = 0.5 * fmadd(alpha, st[j][g], F[g]);
+            fm[j][q] = 0.5 * fmadd(-alpha, st[j][g], F[g]);
         }
     }
     /* Characteristic projection at the Roe state of cells i and i+1. */
@@ -526,7 +528,7 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
     /* Back to conserved variables: F^ = R f^. */
     for (int q = 0; q < nc; ++q) {
         T acc = Rm[q][0] * fh[0];
-        for (int s = 1; s < nc; ++s) acc = acc + Rm[q][s] * fh[s];
+        for (int s = 1; s < nc; ++s) acc = fmadd(Rm[q][s], fh[s], acc);
         Fhat[perm[q]] = acc;
     }
 }

@@ -46,8 +46,8 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
 #pragma unroll
     for (int qq = 0; qq < NC; ++qq) {
         const int g = LO::nat(qq);
-        ext[(size_t)qq * cap + idx] = 0.5 * (Fl[g] + alpha * q[g]);
-        ext[(size_t)(NC + qq) * cap + idx] = 0.5 * (Fl[g] - alpha * q[g]);
+        ext[(size_t)qq * cap + idx] = 0.5 * __builtin_fma(alpha, q[g], Fl[g]);
+        ext[(size_t)(NC + qq) * cap + idx] = 0.5 * __builtin_fma(-alpha, q[g], Fl[g]);
     }
     ext[(size_t)(2 * NC) * cap + idx] = cr_sqrt(rho);
 #pragma unroll
@@ -212,26 +212,28 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
             if (masks != nullptr) *masks |= (code >> 5) << (3 * (2 * s + sg));
             fh = sg ? fh + r : r;
         }
-        // accumulate R[:, s] * fh in local order
+        // accumulate R[:, s] * fh in local order, as fused multiply-adds
+        // (unit entries: plain adds; the first field's products are exact
+        // additions to zero)
         if (acoustic) {
             const bool minus = (s == 0);
             Fh[0] = Fh[0] + fh;
-            Fh[1] = Fh[1] + (minus ? (R.un - R.cs) : (R.un + R.cs)) * fh;
+            Fh[1] = __builtin_fma(minus ? (R.un - R.cs) : (R.un + R.cs), fh, Fh[1]);
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + R.ut[kk - 1] * fh;
-            Fh[NC - 1] = Fh[NC - 1] + (minus ? (R.Hb - R.unc) : (R.Hb + R.unc)) * fh;
+            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = __builtin_fma(R.ut[kk - 1], fh, Fh[1 + kk]);
+            Fh[NC - 1] = __builtin_fma(minus ? (R.Hb - R.unc) : (R.Hb + R.unc), fh, Fh[NC - 1]);
         } else if (entropy) {
             Fh[0] = Fh[0] + fh;
-            Fh[1] = Fh[1] + R.un * fh;
+            Fh[1] = __builtin_fma(R.un, fh, Fh[1]);
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = Fh[1 + kk] + R.ut[kk - 1] * fh;
-            Fh[NC - 1] = Fh[NC - 1] + R.hq2 * fh;
+            for (int kk = 1; kk < ND; ++kk) Fh[1 + kk] = __builtin_fma(R.ut[kk - 1], fh, Fh[1 + kk]);
+            Fh[NC - 1] = __builtin_fma(R.hq2, fh, Fh[NC - 1]);
         } else {
 #pragma unroll
             for (int kk = 1; kk < ND; ++kk) {
                 if (s == 1 + kk) {
                     Fh[1 + kk] = Fh[1 + kk] + fh;
-                    Fh[NC - 1] = Fh[NC - 1] + R.ut[kk - 1] * fh;
+                    Fh[NC - 1] = __builtin_fma(R.ut[kk - 1], fh, Fh[NC - 1]);
                 }
             }
         }
