@@ -822,7 +822,7 @@ def main():
         summarize_trace(*args.summarize_trace[:2])
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); sharding over several "
+        print("bench.py: the library runs on exactly one GPU (--gpus 1); sharding over several "
               "GPUs is a design note only", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
