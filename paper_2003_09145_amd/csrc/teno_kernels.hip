@@ -241,7 +241,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
         if (lane == 0 && v != 0ull) atomicAdd(A.digest, v);
     }
-    __syncthreads();
 
     // ---- flux difference and epilogue ---------------------------------------
     // Face j of the chunk (j >= 1) updates its left cell from the fluxes at
@@ -262,15 +261,31 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         fh_c = smem + 24 + (size_t)cc * per_wave;
         colbase_j = (col0 + cc) * A.col_step;
     }
+    // The cell's partial RHS, stage input and u^n are loaded before the
+    // barrier, so that their latency overlaps the wait: each cell is read and
+    // written by its own thread only, and the stencils read a different array.
+    const int64_t cell = colbase_j + blj * A.line_step + (phij - 1) * A.stride;
+    double r_in[NC], u_in[NC], u_n[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r_in[c] = u_in[c] = u_n[c] = 0.0;
+    if (upd) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const size_t at = (size_t)c * A.ncell + cell;
+            if (A.Rin != nullptr) r_in[c] = A.Rin[at];
+            if (A.rk != 0) u_in[c] = A.U[at];
+            if (A.rk >= 2) u_n[c] = A.Un[at];
+        }
+    }
+    __syncthreads();
+
     if (upd) {
         const double rdx = rcp_nr(A.dx);
-        const int64_t cell = colbase_j + blj * A.line_step + (phij - 1) * A.stride;
         double r[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double diff = fh_c[c * 64 + jj] - fh_c[c * 64 + jj - 1];
-            const double prev = (A.Rin != nullptr) ? A.Rin[c * A.ncell + cell] : 0.0;
-            r[c] = prev - cr_div_r(diff, A.dx, rdx);
+            r[c] = r_in[c] - cr_div_r(diff, A.dx, rdx);
         }
         if (A.add_source) {
             // gravity: rho g_d on each momentum, m . g on the energy (after the
@@ -294,11 +309,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const size_t at = (size_t)c * A.ncell + cell;
                 double v;
                 if (A.rk == 1) {
-                    v = A.U[at] + h * r[c];
+                    v = u_in[c] + h * r[c];
                 } else if (A.rk == 2) {
-                    v = (0.75 * A.Un[at] + 0.25 * A.U[at]) + 0.25 * (h * r[c]);
+                    v = (0.75 * u_n[c] + 0.25 * u_in[c]) + 0.25 * (h * r[c]);
                 } else {
-                    v = ((1.0 / 3.0) * A.Un[at] + (2.0 / 3.0) * A.U[at]) + (2.0 / 3.0) * (h * r[c]);
+                    v = ((1.0 / 3.0) * u_n[c] + (2.0 / 3.0) * u_in[c]) + (2.0 / 3.0) * (h * r[c]);
                 }
                 A.Uout[at] = v;
             }
