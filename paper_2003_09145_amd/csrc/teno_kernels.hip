@@ -178,7 +178,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int cc = COOP ? (int)(threadIdx.x % W) : wave;  // column slot within the block
     const int64_t colbase_c = (col0 + cc) * A.col_step;
     double* ext_c = smem + 24 + (size_t)cc * per_wave;
-    for (int idx = COOP ? (int)(threadIdx.x / W) : lane; idx < count; idx += 64) {
+    // conserved state of ext cell idx (ghost images mapped, fixed states)
+    auto load_cell = [&](int idx, double* q) {
         const int jq = je0 + idx;
         const int bw = div_by(jq, A.m6, A.s6);
         const int64_t b = be0 + bw;
@@ -189,7 +190,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (A.bnd != nullptr && (j < 0 || j >= n))
             kind = boundary_kind(A.bnd, A.ctrl, A.stage, DIR, j < 0 ? 0 : 1,
                                  colbase_c + b * A.line_step, A.nx, A.ny, A.dxa, &fixed);
-        double q[NC];
         if (fixed != nullptr) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) q[c] = fixed[c];
@@ -200,7 +200,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
             if (flip) q[1 + DIR] = -q[1 + DIR];
         }
-        stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, idx);
+    };
+    // one cell ahead: the next cell's loads are in flight while this one's
+    // primitives, fluxes and splits are computed
+    int idx = COOP ? (int)(threadIdx.x / W) : lane;
+    double qn[NC];
+    if (idx < count) load_cell(idx, qn);
+    while (idx < count) {
+        double q[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = qn[c];
+        const int cur = idx;
+        idx += 64;
+        if (idx < count) load_cell(idx, qn);
+        stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, cur);
     }
     }
     __syncthreads();
