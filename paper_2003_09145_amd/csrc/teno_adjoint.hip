@@ -131,16 +131,31 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     const double gm1 = A.sch.gamma - 1.0;
 
     // ---- stage the chunk's cells exactly as the forward sweep does ---------
-    for (int idx = lane; idx < count; idx += 64) {
-        bool flip;
-        const int64_t cell = ext_source(A, colbase, be0, je0 + idx, &flip);
-        double q[NC];
+    // conserved state of staged cell idx as stored (ghost flip not applied)
+    auto load_ext = [&](int idx, double* q, bool* flip) {
+        const int64_t cell = ext_source(A, colbase, be0, je0 + idx, flip);
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
-        if (flip) q[1 + DIR] = -q[1 + DIR];
-        stage_cell<ND, DIR>(q, alpha, gm1, ext, cap, idx);
+    };
+    {
+        // one cell ahead: the next cell's loads are in flight meanwhile
+        int idx = lane;
+        double qn[NC];
+        bool fn = false;
+        if (idx < count) load_ext(idx, qn, &fn);
+        while (idx < count) {
+            double q[NC];
 #pragma unroll
-        for (int r = 0; r < NV; ++r) acc[(size_t)r * cap + idx] = 0.0;
+            for (int c = 0; c < NC; ++c) q[c] = qn[c];
+            const bool flip = fn;
+            const int cur = idx;
+            idx += 64;
+            if (idx < count) load_ext(idx, qn, &fn);
+            if (flip) q[1 + DIR] = -q[1 + DIR];
+            stage_cell<ND, DIR>(q, alpha, gm1, ext, cap, cur);
+#pragma unroll
+            for (int r = 0; r < NV; ++r) acc[(size_t)r * cap + cur] = 0.0;
+        }
     }
     __syncthreads();
 
@@ -329,15 +344,22 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk) cr[(size_t)(1 + kk) * cap + 3] += ur_b[kk];
     }
+    // the first staged cell of the per-cell phase is loaded before the barrier
+    int idx3 = lane;
+    double qn3[NC];
+    bool fn3 = false;
+    if (idx3 < count) load_ext(idx3, qn3, &fn3);
     __syncthreads();
 
     // ---- per staged cell: the cell's own Jacobian, once ---------------------
-    for (int idx = lane; idx < count; idx += 64) {
-        bool flip;
-        const int64_t cell = ext_source(A, colbase, be0, je0 + idx, &flip);
+    while (idx3 < count) {
         double q[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
+        for (int c = 0; c < NC; ++c) q[c] = qn3[c];
+        const bool flip = fn3;
+        const int idx = idx3;
+        idx3 += 64;
+        if (idx3 < count) load_ext(idx3, qn3, &fn3);
         if (flip) q[1 + DIR] = -q[1 + DIR];
         const double rho = q[0], ri = 1.0 / rho, E = q[NC - 1];
         double u[ND], uu2 = 0.0;
