@@ -153,20 +153,25 @@ __device__ __forceinline__ double char_rec(const double* __restrict__ ext, int c
     constexpr int NC = ND + 2;
     const bool shear = !(s == 0 || s == NC - 1) && s != 1;
     const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
+    // the field-type test outside the stencil loop, so that the five points'
+    // reads form one block the scheduler can issue ahead of their products
     double v[5];
+    if (shear) {  // the unit entry: a plain add, as the oracle's fma by 1
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const int cj = sg ? 5 - j : j;
-        double acc;
-        if (shear) {  // the unit entry: a plain add, as the oracle's fma by 1
-            acc = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
-        } else {
-            acc = Lr[0] * fb[cj];
+        for (int j = 0; j < 5; ++j) {
+            const int cj = sg ? 5 - j : j;
+            v[j] = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int cj = sg ? 5 - j : j;
+            double acc = Lr[0] * fb[cj];
 #pragma unroll
             for (int qq = 1; qq < NC; ++qq)
                 acc = __builtin_fma(Lr[qq], fb[(size_t)qq * cap + cj], acc);
+            v[j] = acc;
         }
-        v[j] = acc;
     }
     return teno5_rec_fast<A5>(sch, dk, omega, v[0], v[1], v[2], v[3], v[4], code);
 }

@@ -580,16 +580,23 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     // the fixed-stride variant; along y and z a block stages and updates four
     // neighbouring columns, which needs whole blocks of columns (8- and
     // 16-column blocks, with 71 / 142 KB of LDS, measured no faster)
-    if (!digest && A.ext_cap == kCapLong && DIR == 0) {
-        // x: every wave is independent, so one-wave blocks let a finished
-        // wave's slot be refilled at once
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, kCapLong, A5>), dim3((unsigned)A.nchunks),
-                           dim3(64), table + per_wave, st, A);
-    } else if (!digest && A.ext_cap == kCapLong && A.ncols % 4 == 0) {
-        const int64_t blocks = (A.nchunks + 3) / 4;
-        hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong, A5>), dim3((unsigned)blocks),
-                           dim3(256), table + 4 * per_wave, st, A);
-    } else if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
+    if constexpr (DIR == 0) {
+        if (!digest && A.ext_cap == kCapLong) {
+            // x: every wave is independent, so one-wave blocks let a finished
+            // wave's slot be refilled at once
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, kCapLong, A5>),
+                               dim3((unsigned)A.nchunks), dim3(64), table + per_wave, st, A);
+            return hipGetLastError();
+        }
+    } else {
+        if (!digest && A.ext_cap == kCapLong && A.ncols % 4 == 0) {
+            const int64_t blocks = (A.nchunks + 3) / 4;
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong, A5>), dim3((unsigned)blocks),
+                               dim3(256), table + 4 * per_wave, st, A);
+            return hipGetLastError();
+        }
+    }
+    if (table + 4 * per_wave <= (size_t)kMaxLdsPerBlock) {
         const int64_t blocks = (A.nchunks + 3) / 4;
         if (digest)
             hipLaunchKernelGGL((k_sweep<ND, DIR, 4, true, 0, A5>), dim3((unsigned)blocks), dim3(256),
