@@ -589,6 +589,14 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
             return hipGetLastError();
         }
     } else {
+        if constexpr (DIR == 2) {
+            if (!digest && A.ext_cap == kCapLong && A.ncols % 8 == 0) {
+                const int64_t blocks = (A.nchunks + 7) / 8;
+                hipLaunchKernelGGL((k_sweep<ND, DIR, 8, false, kCapLong, A5>),
+                                   dim3((unsigned)blocks), dim3(512), table + 8 * per_wave, st, A);
+                return hipGetLastError();
+            }
+        }
         if (!digest && A.ext_cap == kCapLong && A.ncols % 4 == 0) {
             const int64_t blocks = (A.nchunks + 3) / 4;
             hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapLong, A5>), dim3((unsigned)blocks),
