@@ -118,24 +118,29 @@ __device__ __forceinline__ double cr_sqrt_exact(double x) {
 // accepted s is the nearest double (s not a power of two, both neighbours one
 // ulp away; the bound is exact and normal).  Everything else takes the exact
 // neighbour test on the compiler's root.
+// Fast phase: *s is the refined root (for x outside the safe range, any
+// value); true when it is certified.  The exact phase is cr_sqrt_exact.
+__device__ __forceinline__ bool sqrt_fast(double x, double* sout) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y;
+    double h = 0.5 * y;
+    const double e = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, e, s);
+    h = __builtin_fma(h, e, h);
+    double d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    const double r = __builtin_fma(-s, s, x);
+    int es;
+    const double ms = frexp(s, &es);
+    const double u = ldexp(1.0, es - 53);  // ulp(s)
+    *sout = s;
+    return (x >= 0x1p-900 && x <= 0x1p900) && fabs(r) < ldexp(s - u, es - 53) && ms > 0.5;
+}
 __device__ __forceinline__ double cr_sqrt(double x) {
-    if (x >= 0x1p-900 && x <= 0x1p900) {
-        const double y = __builtin_amdgcn_rsq(x);
-        double s = x * y;
-        double h = 0.5 * y;
-        const double e = __builtin_fma(-h, s, 0.5);
-        s = __builtin_fma(s, e, s);
-        h = __builtin_fma(h, e, h);
-        double d = __builtin_fma(-s, s, x);
-        s = __builtin_fma(d, h, s);
-        d = __builtin_fma(-s, s, x);
-        s = __builtin_fma(d, h, s);
-        const double r = __builtin_fma(-s, s, x);
-        int es;
-        const double ms = frexp(s, &es);
-        const double u = ldexp(1.0, es - 53);                 // ulp(s)
-        if (fabs(r) < ldexp(s - u, es - 53) && ms > 0.5) return s;
-    }
+    double s;
+    if (sqrt_fast(x, &s)) return s;
     return cr_sqrt_exact(x);
 }
 
@@ -151,12 +156,19 @@ __device__ __forceinline__ double rcp_nr(double b) {
 // Correctly rounded a / b from rb = rcp_nr(b): q0 = a rb, one Markstein step
 // q1 = q0 + (a - q0 b) rb (faithful), then the exact-remainder correction of
 // cr_div.  Outside the safe range it defers to cr_div.
-__device__ __forceinline__ double cr_div_r(double a, double b, double rb) {
+//
+// Split in two phases so that several independent divisions share one
+// (rarely taken) correction branch: div_r_fast forms q1 and its remainder and
+// reports whether the fast test already certifies q1; div_r_fix corrects a
+// quotient the test did not certify.
+__device__ __forceinline__ bool div_r_fast(double a, double b, double rb, double* q, double* r) {
     const double q0 = a * rb;
     const double e = __builtin_fma(-q0, b, a);
-    const double q = __builtin_fma(e, rb, q0);
-    const double r = __builtin_fma(-q, b, a);  // exact in the safe range
-    if (quotient_is_nearest(q, b, r)) return q;
+    *q = __builtin_fma(e, rb, q0);
+    *r = __builtin_fma(-*q, b, a);  // exact in the safe range
+    return quotient_is_nearest(*q, b, *r);
+}
+__device__ __forceinline__ double div_r_fix(double a, double b, double q, double r) {
     if (!(in_safe_range(a) && in_safe_range(b) && in_safe_range(q))) return cr_div(a, b);
     if (r == 0.0) return q;
     const bool up = (r > 0.0) == (b > 0.0);
@@ -166,6 +178,29 @@ __device__ __forceinline__ double cr_div_r(double a, double b, double rb) {
     if (ar > ah) return qn;
     if (ar == ah) return (__double_as_longlong(q) & 1ll) ? qn : q;
     return q;
+}
+__device__ __forceinline__ double cr_div_r(double a, double b, double rb) {
+    double q, r;
+    if (div_r_fast(a, b, rb, &q, &r)) return q;
+    return div_r_fix(a, b, q, r);
+}
+// q[i] = a[i] / b correctly rounded for N independent dividends.
+template <int N>
+__device__ __forceinline__ void cr_div_r_n(const double (&a)[N], double b, double rb,
+                                           double (&q)[N]) {
+    double r[N];
+    bool ok[N];
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        ok[i] = div_r_fast(a[i], b, rb, &q[i], &r[i]);
+        all = all && ok[i];
+    }
+    if (!all) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (!ok[i]) q[i] = div_r_fix(a[i], b, q[i], r[i]);
+    }
 }
 
 // TENO weights of eq 2.15 for each cutoff mask, omega_k = delta_k c_k / D with

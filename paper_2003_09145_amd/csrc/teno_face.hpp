@@ -26,8 +26,26 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
     const double rho = q[0];
     double u[ND];
     const double rrho = rcp_nr(rho);
+    // the velocity quotients and sqrt(rho) are independent: their fast
+    // phases run together and share one correction branch
+    double srho;
+    {
+        double r[ND];
+        bool ok[ND];
+        bool all = sqrt_fast(rho, &srho);
+        const bool sok = all;
 #pragma unroll
-    for (int kk = 0; kk < ND; ++kk) u[kk] = cr_div_r(q[1 + kk], rho, rrho);
+        for (int kk = 0; kk < ND; ++kk) {
+            ok[kk] = div_r_fast(q[1 + kk], rho, rrho, &u[kk], &r[kk]);
+            all = all && ok[kk];
+        }
+        if (!all) {
+            if (!sok) srho = cr_sqrt_exact(rho);
+#pragma unroll
+            for (int kk = 0; kk < ND; ++kk)
+                if (!ok[kk]) u[kk] = div_r_fix(q[1 + kk], rho, u[kk], r[kk]);
+        }
+    }
     double mu = q[1] * u[0];
 #pragma unroll
     for (int kk = 1; kk < ND; ++kk) mu = mu + q[1 + kk] * u[kk];
@@ -49,7 +67,7 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
         ext[(size_t)qq * cap + idx] = 0.5 * __builtin_fma(alpha, q[g], Fl[g]);
         ext[(size_t)(NC + qq) * cap + idx] = 0.5 * __builtin_fma(-alpha, q[g], Fl[g]);
     }
-    ext[(size_t)(2 * NC) * cap + idx] = cr_sqrt(rho);
+    ext[(size_t)(2 * NC) * cap + idx] = srho;
 #pragma unroll
     for (int kk = 0; kk < ND; ++kk) ext[(size_t)(2 * NC + 1 + kk) * cap + idx] = u[kk];
     ext[(size_t)(2 * NC + 1 + ND) * cap + idx] = H;
@@ -93,9 +111,18 @@ __device__ __forceinline__ FaceRoe<ND> face_roe(const double* __restrict__ ext, 
 #pragma unroll
     for (int kk = 1; kk < ND; ++kk) R.q2 = R.q2 + R.ub[kk] * R.ub[kk];
     R.c2 = gm1 * (R.Hb - 0.5 * R.q2);
-    R.cs = cr_sqrt(R.c2);
+    {
+        // c = sqrt(c2) and b1 = (gamma - 1) / c2 are independent: one
+        // correction branch for both
+        double r;
+        const bool sok = sqrt_fast(R.c2, &R.cs);
+        const bool bok = div_r_fast(gm1, R.c2, rcp_nr(R.c2), &R.b1, &r);
+        if (!(sok && bok)) {
+            if (!sok) R.cs = cr_sqrt_exact(R.c2);
+            if (!bok) R.b1 = div_r_fix(gm1, R.c2, R.b1, r);
+        }
+    }
     R.ci = cr_div_r(1.0, R.cs, rcp_nr(R.cs));
-    R.b1 = cr_div_r(gm1, R.c2, rcp_nr(R.c2));
     R.b2 = (0.5 * R.q2) * R.b1;
     R.un = R.ub[DIR];
 #pragma unroll

@@ -294,12 +294,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     if (upd) {
         const double rdx = rcp_nr(A.dx);
-        double r[NC];
+        double diff[NC], dq[NC], r[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double diff = fh_c[c * 64 + jj] - fh_c[c * 64 + jj - 1];
-            r[c] = r_in[c] - cr_div_r(diff, A.dx, rdx);
-        }
+        for (int c = 0; c < NC; ++c) diff[c] = fh_c[c * 64 + jj] - fh_c[c * 64 + jj - 1];
+        cr_div_r_n<NC>(diff, A.dx, rdx, dq);  // independent quotients, one correction branch
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] = r_in[c] - dq[c];
         if (A.add_source) {
             // gravity: rho g_d on each momentum, m . g on the energy (after the
             // flux differences of every axis)
