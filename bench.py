@@ -115,6 +115,11 @@ def sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
+# waves per block of the fixed-stride sweeps on a 256^3 grid: x one-wave
+# blocks, y four neighbouring columns, z eight
+SWEEP_WAVES = {0: 1, 1: 4, 2: 8}
+
+
 def load_traffic(kernel: str):
     """Counter-measured HBM bytes per launch of `kernel` from the committed
     summary, or None when the sweep sources changed since it was taken."""
@@ -184,7 +189,8 @@ def headline(args, B, W, torch):
     fused = dom == 2
     flops = sweep_flops(3, n3, dom, fused_rk=fused)
     achieved = flops / (per_axis[dom] * 1e-3) / 1e12
-    kname = f"k_sweep<3,{dom},4,false>"  # the plain (digest-free) instantiation
+    # the plain (digest-free) instantiation; waves per block by axis at 256^3
+    kname = f"k_sweep<3,{dom},{SWEEP_WAVES[dom]},false>"
     traffic = load_traffic(kname)
     alg_bytes = sweep_bytes(3, n3, dom, fused_rk=fused)
     roofline = {
@@ -679,7 +685,7 @@ def summarize_counters(d):
     n3 = [256] * 3
     lines = [
         "# HBM traffic and FP64 VALU counters of the 3D sweep kernels, 256^3 turbulence",
-        "# (k_sweep<3,d,4>: axis d; axis z carries the fused RK stage update)",
+        "# (k_sweep<3,d,W>: axis d, W waves per block; axis z carries the fused RK stage update)",
         "#",
         "# commands (from the repository root, after cd /tmp && export TMPDIR=/tmp; $OUT is any",
         "# output directory):",
