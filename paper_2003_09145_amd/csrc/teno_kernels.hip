@@ -135,13 +135,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
     const int64_t colbase = col * A.col_step;
     const int cap = CAPC ? CAPC : A.ext_cap;
+    // XCOOP (x sweep, CAPC = kCapBlock): the W waves of a block take W
+    // consecutive chunks of the face stream, whose stencil windows overlap by
+    // 6 cells; the block stages their union once, in one shared buffer, and
+    // each wave reads its faces' stencils at its own offset in it.
+    constexpr bool XCOOP = (DIR == 0) && (CAPC > 74);
     double* omega = smem;  // 24 doubles: eq 2.15 weights per cutoff mask
-    const int per_wave = (cap * NV > 64 * NC) ? cap * NV : 64 * NC;
-    double* ext = smem + 24 + (size_t)wave * per_wave;
-    // The face fluxes reuse the wave's own stencil buffer: LDS operations of
-    // one wave complete in order, so every stencil read of the wave precedes
-    // the first face-flux write.
-    double* fhs = ext;
+    const int per_wave = XCOOP ? 64 * NC : ((cap * NV > 64 * NC) ? cap * NV : 64 * NC);
+    double* ext = XCOOP ? smem + 24 : smem + 24 + (size_t)wave * per_wave;
+    // The face fluxes reuse the stencil buffer: LDS operations of one wave
+    // complete in order, so every stencil read of the wave precedes its first
+    // face-flux write (XCOOP: the buffer is shared, and a block barrier
+    // separates every wave's stencil reads from the flux writes).
+    double* fhs = XCOOP ? smem + 24 + (size_t)wave * per_wave : ext;
     if (threadIdx.x < 24) omega[threadIdx.x] = kOmega[threadIdx.x / 3][threadIdx.x % 3];
 
     const int64_t F0 = k * kCellsPerChunk;
@@ -156,12 +162,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int wraps = div_by(tq, A.m1, A.s1);
     const int64_t bl = bl0 + wraps;                        // line of this lane's face
     const int64_t phi = tq - wraps * (int)np1;             // face index in the line (i + 1)
-    const int64_t e_lo = F0 + 5 * bl0;
-    int64_t Flast = F0 + 63;
+    // staged window: the wave's chunk, or (XCOOP) the block's W chunks
+    const int64_t F0w = XCOOP ? lb * W * kCellsPerChunk : F0;
+    const int64_t bl0w =
+        XCOOP ? (A.div32 ? (int64_t)div_by((int)F0w, A.m1, A.s1) : F0w / np1) : bl0;
+    const int64_t e_lo = F0w + 5 * bl0w;
+    int64_t Flast = F0w + 63 * (XCOOP ? W : 1);
     if (Flast > A.ftot - 1) Flast = A.ftot - 1;
     const int64_t e_hi =
         Flast + 5 * (A.div32 ? (int64_t)div_by((int)Flast, A.m1, A.s1) : Flast / np1) + 6;
-    const int count = wave_ok ? (int)(e_hi - e_lo) : 0;
+    const int count = (XCOOP || wave_ok) ? (int)(e_hi - e_lo) : 0;
 
     // ---- stage per-cell quantities of the ext cells [e_lo, e_hi) ----------
     const double alpha = A.alpha[DIR];
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     {
     const int cc = COOP ? (int)(threadIdx.x % W) : wave;  // column slot within the block
     const int64_t colbase_c = (col0 + cc) * A.col_step;
-    double* ext_c = smem + 24 + (size_t)cc * per_wave;
+    double* ext_c = XCOOP ? ext : smem + 24 + (size_t)cc * per_wave;
     // conserved state of ext cell idx (ghost images mapped, fixed states)
     auto load_cell = [&](int idx, double* q) {
         const int jq = je0 + idx;
@@ -203,7 +213,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     };
     // one cell ahead: the next cell's loads are in flight while this one's
     // primitives, fluxes and splits are computed
-    int idx = COOP ? (int)(threadIdx.x / W) : lane;
+    int idx = COOP ? (int)(threadIdx.x / W) : XCOOP ? (int)threadIdx.x : lane;
+    constexpr int kStep = XCOOP ? 64 * W : 64;
     double qn[NC];
     if (idx < count) load_cell(idx, qn);
     while (idx < count) {
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = qn[c];
         const int cur = idx;
-        idx += 64;
+        idx += kStep;
         if (idx < count) load_cell(idx, qn);
         stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, cur);
     }
@@ -224,6 +235,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const bool want_digest =
         DIGEST && A.digest != nullptr && (A.ctrl == nullptr || A.ctrl->want_digest);
     unsigned long long sig = 0ull;
+    double Fh[NC];
     if (valid) {
         const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of cell i-2
         // oracle line numbering of the decision dump: x: k*ny + j; y: k*nx + i; z: j*nx + i
@@ -232,12 +244,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
             const int64_t gline = (DIR == 0) ? bl : bl * A.ncols + col;
             o8 = A.dump + (gline * np1 + phi) * (2 * NC);
         }
-        double Fh[NC];
         uint32_t masks = 0;
         face_flux<ND, DIR, A5>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
                            want_digest ? &masks : nullptr);
+        if constexpr (!XCOOP) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
+            for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
+        }
         if (want_digest) {
             // the key names the step and stage as well as the face, so masks
             // that move in time past a face change the digest
@@ -253,6 +266,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
         for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
         if (lane == 0 && v != 0ull) atomicAdd(A.digest, v);
+    }
+
+    if constexpr (XCOOP) {
+        __syncthreads();  // every wave's stencil reads precede the flux writes
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fhs[c * 64 + lane] = Fh[c];
+        }
     }
 
     // ---- flux difference and epilogue ---------------------------------------
@@ -582,10 +603,13 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     // 16-column blocks, with 71 / 142 KB of LDS, measured no faster)
     if constexpr (DIR == 0) {
         if (!digest && A.ext_cap == kCapLong) {
-            // x: every wave is independent, so one-wave blocks let a finished
-            // wave's slot be refilled at once
-            hipLaunchKernelGGL((k_sweep<ND, DIR, 1, false, kCapLong, A5>),
-                               dim3((unsigned)A.nchunks), dim3(64), table + per_wave, st, A);
+            // x: 4 consecutive chunks per block staged once as the union of
+            // their windows (4 x 63 faces span at most 5 lines when n >= 63:
+            // 252 + 6 + 5 x 4 = 278 cells)
+            constexpr int kCapBlock = 280;
+            const int64_t blocks = (A.nchunks + 3) / 4;
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapBlock, A5>), dim3((unsigned)blocks),
+                               dim3(256), table + (size_t)NV * kCapBlock * sizeof(double), st, A);
             return hipGetLastError();
         }
     } else {
