@@ -237,9 +237,9 @@ int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
 
 /* teno_step with timing marks, for profiling the launches of a step inside a
  * longer timed region.  events: 2 * 3 * ndim hipEvent_t handles created by the
- * caller (entries may be null); events[2 * (3 * s + d)] is recorded on
+ * caller (entries may be null); events[2 * (ndim * s + d)] is recorded on
  * `stream` right before the sweep kernel of axis d in RK stage s and
- * events[2 * (3 * s + d) + 1] right after it.  Results are identical to
+ * events[2 * (ndim * s + d) + 1] right after it.  Results are identical to
  * teno_step. */
 int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
                     void* ws_dev, size_t ws_bytes, void* const* events, void* stream);

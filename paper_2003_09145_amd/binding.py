@@ -315,7 +315,7 @@ def teno_step(g, U, ctrl, ws, stream=None):
 
 
 def teno_step_timed(g, U, ctrl, ws, events, stream=None):
-    """teno_step recording events[2 * (3 * s + d)] / [... + 1] (torch.cuda.Event
+    """teno_step recording events[2 * (ndim * s + d)] / [... + 1] (torch.cuda.Event
     objects, already recorded once so that they exist) around the sweep of
     axis d in stage s."""
     n = 2 * 3 * g.ndim

@@ -886,8 +886,8 @@ static int step_impl(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, s
                 A.Uout = stage_out[s];
                 A.add_source = 1;
             }
-            void* ev0 = events ? events[2 * (3 * s + d)] : nullptr;
-            void* ev1 = events ? events[2 * (3 * s + d) + 1] : nullptr;
+            void* ev0 = events ? events[2 * (g->ndim * s + d)] : nullptr;
+            void* ev1 = events ? events[2 * (g->ndim * s + d) + 1] : nullptr;
             if (ev0 != nullptr && hipEventRecord((hipEvent_t)ev0, st) != hipSuccess)
                 return TENO_ERR_DEVICE;
             if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;

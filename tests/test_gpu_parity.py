@@ -209,6 +209,32 @@ def test_step_parity(torch, B, orc, name, steps):
     assert np.array_equal(Ug, Uc)
 
 
+@pytest.mark.parametrize("name", ["1d_sod200", "2d_riemann3_96x80", "3d_random21x18x13_mixed"])
+def test_step_timed_matches_step(torch, B, name):
+    # teno_step_timed: 2 * 3 * ndim events, pair (ndim * s + d) around the
+    # sweep of axis d in stage s; the state equals teno_step's bit for bit
+    prob, U = CASES[name]()
+    nd = prob.ndim
+    plain = B.Solver(prob)
+    timed = B.Solver(prob)
+    plain.init(0.0, 1e9, 0.5)
+    timed.init(0.0, 1e9, 0.5)
+    u0 = torch.from_numpy(U.copy()).cuda()
+    u1 = torch.from_numpy(U.copy()).cuda()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 3 * nd)]
+    for e in evs:
+        e.record(stream)
+    for _ in range(2):
+        plain.step(u0)
+        timed.step(u1, events=evs)
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1)
+    for s in range(3):
+        for d in range(nd):
+            assert evs[2 * (nd * s + d)].elapsed_time(evs[2 * (nd * s + d) + 1]) >= 0.0
+
+
 def test_sod_run_to_t_end(torch, B, orc):
     from oracle import riemann
     prob, U = W.sod(200)
