@@ -261,9 +261,14 @@ constexpr double kDecisionMargin = 0x1p-40;
 __device__ __forceinline__ double teno5a_cutoff(const SchemeParams& S, double a, double b,
                                                 double c, double d, double e, int* k) {
     const double df0 = b - a, df1 = c - b, df2 = d - c, df3 = e - d;
-    const double eta0 = cr_div(2.0 * fabs(df1 * df0) + S.epsA, (df1 * df1 + df0 * df0) + S.epsA);
-    const double eta1 = cr_div(2.0 * fabs(df2 * df1) + S.epsA, (df2 * df2 + df1 * df1) + S.epsA);
-    const double eta2 = cr_div(2.0 * fabs(df3 * df2) + S.epsA, (df3 * df3 + df2 * df2) + S.epsA);
+    // 2 x and 4 x are exact, so the fused forms below round exactly as the
+    // oracle's product-then-add
+    const double eta0 =
+        cr_div(__builtin_fma(2.0, fabs(df1 * df0), S.epsA), (df1 * df1 + df0 * df0) + S.epsA);
+    const double eta1 =
+        cr_div(__builtin_fma(2.0, fabs(df2 * df1), S.epsA), (df2 * df2 + df1 * df1) + S.epsA);
+    const double eta2 =
+        cr_div(__builtin_fma(2.0, fabs(df3 * df2), S.epsA), (df3 * df3 + df2 * df2) + S.epsA);
     double eh = eta0;
     if (eta1 < eh) eh = eta1;
     if (eta2 < eh) eh = eta2;
@@ -271,7 +276,7 @@ __device__ __forceinline__ double teno5a_cutoff(const SchemeParams& S, double a,
     const double mA = 1.0 - (q < 1.0 ? q : 1.0);
     const double om = 1.0 - mA;
     const double om2 = om * om;
-    const double g = (om2 * om2) * (1.0 + 4.0 * mA);
+    const double g = (om2 * om2) * __builtin_fma(4.0, mA, 1.0);
     const double bA = S.a1 - S.a2 * (1.0 - g);
     const int kk = (bA >= 0.0) ? (int)floor(bA) : S.kA_nan;
     *k = kk;
@@ -340,13 +345,15 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
                                                  const double* __restrict__ omega_lds,
                                                  double a, double b, double c, double d,
                                                  double e, uint32_t* code) {
-    // sums of products as fused multiply-adds, in the oracle's order
-    const double s01 = (a - 2.0 * b) + c;
-    const double s02 = __builtin_fma(3.0, c, a - 4.0 * b);
-    const double s11 = (b - 2.0 * c) + d;
+    // sums of products as fused multiply-adds, in the oracle's order; a - 2 b
+    // and a - 4 b are single roundings either way (2 b and 4 b are exact for
+    // |b| below 2^1021), so they are fused here too
+    const double s01 = __builtin_fma(-2.0, b, a) + c;
+    const double s02 = __builtin_fma(3.0, c, __builtin_fma(-4.0, b, a));
+    const double s11 = __builtin_fma(-2.0, c, b) + d;
     const double s12 = b - d;
-    const double s21 = (c - 2.0 * d) + e;
-    const double s22 = __builtin_fma(3.0, c, e - 4.0 * d);
+    const double s21 = __builtin_fma(-2.0, d, c) + e;
+    const double s22 = __builtin_fma(3.0, c, __builtin_fma(-4.0, d, e));
     const double beta0 = __builtin_fma(kB13_12 * s01, s01, kB1_4 * (s02 * s02));
     const double beta1 = __builtin_fma(kB13_12 * s11, s11, kB1_4 * (s12 * s12));
     const double beta2 = __builtin_fma(kB13_12 * s21, s21, kB1_4 * (s22 * s22));
