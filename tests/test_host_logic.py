@@ -50,3 +50,49 @@ def test_div_magic_matches_integer_division(tmp_path):
     subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, "-o", str(exe), str(src)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
+
+
+FUSE_HARNESS = r'''
+#include <initializer_list>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+// The kernels fuse a - 2 b and a - 4 b into fma(-2, b, a) and fma(-4, b, a)
+// where the oracle forms the product first; with |b| below 2^1021 the
+// product is exact, so both round once to the same double.
+static double bits(unsigned long long u) { double d; memcpy(&d, &u, 8); return d; }
+int main() {
+    unsigned long long s = 12345, n = 0;
+    for (int t = 0; t < 4000000; ++t) {
+        s = s * 6364136223846793005ull + 1442695040888963407ull;
+        unsigned long long ua = s;
+        s = s * 6364136223846793005ull + 1442695040888963407ull;
+        unsigned long long ub = s;
+        // exponents spread over the whole range below 2^1021, subnormals included
+        const double a = bits(ua & ~(0x7ffull << 52) | ((ua >> 52) % 2045ull) << 52);
+        const double b = bits(ub & ~(0x7ffull << 52) | ((ub >> 52) % 2044ull) << 52);
+        const double near_b = (t & 1) ? b : a * 0.5 * (1.0 + ldexp((double)(t % 64), -52));
+        for (double k : {2.0, 4.0}) {
+            const double x = near_b;
+            const double p = a - k * x, f = fma(-k, x, a);
+            if (memcmp(&p, &f, 8) != 0 && !(isnan(p) && isnan(f))) {
+                printf("FAIL %a %a %g\n", a, x, k);
+                return 1;
+            }
+            ++n;
+        }
+    }
+    printf("ok %llu\n", n);
+    return 0;
+}
+'''
+
+
+def test_power_of_two_products_fuse_exactly(tmp_path):
+    src = tmp_path / "fuse.cpp"
+    exe = tmp_path / "fuse"
+    src.write_text(FUSE_HARNESS)
+    subprocess.run(["g++", "-O2", "-std=c++17", "-mfma", "-ffp-contract=off", "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
