@@ -82,6 +82,14 @@ CASES = {
     # nx % 4 != 0: the y sweep falls back to one column per wave
     "2d_random98x70_mixed": lambda: (lambda p: (p, W.random_field(p, seed=11)))(
         W.uniform_problem(2, [98, 70], [0.0, 0.0], [1.0, 1.0], ["transmissive", "periodic"])),
+    # the shortest lines of the fixed-stride sweeps (n = 63: 64 faces per
+    # line, so a 4-chunk x block spans 5 lines), x blocks with a partial last
+    # block, and eight-column z blocks (nx % 8 == 0)
+    "2d_random63x66_mixed": lambda: (lambda p: (p, W.random_field(p, seed=12)))(
+        W.uniform_problem(2, [63, 66], [0.0, 0.0], [1.0, 1.0], ["reflective", "periodic"])),
+    "3d_random72x63x64_mixed": lambda: (lambda p: (p, W.random_field(p, seed=13)))(
+        W.uniform_problem(3, [72, 63, 64], [0.0] * 3, [1.0] * 3,
+                          ["transmissive", "periodic", "reflective"])),
 }
 
 
@@ -193,7 +201,9 @@ def _gpu_steps(torch, B, prob, U, cfl, t_end, nsteps):
 
 @pytest.mark.parametrize("name,steps", [("1d_sod200", 12), ("2d_riemann3_96x80", 4),
                                         ("3d_random21x18x13_mixed", 3), ("3d_turbulence24", 3),
-                                        ("3d_random64x65x70_mixed", 2)])
+                                        ("3d_random64x65x70_mixed", 2),
+                                        ("3d_random72x63x64_mixed", 2),
+                                        ("2d_random63x66_mixed", 3)])
 def test_step_parity(torch, B, orc, name, steps):
     prob, U = CASES[name]()
     Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
