@@ -181,7 +181,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int je0 = (int)(e_lo - be0 * np6);
     // COOP (y and z sweeps, W waves = W neighbouring columns of one line chunk,
     // which the host guarantees): thread t stages column t % W, so a wave's
-    // loads cover 64 / W cells x W neighbouring x (W = 16: whole cache lines).
+    // loads cover 64 / W cells x W neighbouring x (rows of 8 W bytes).
     constexpr bool COOP = (CAPC != 0) && (DIR != 0) && (W >= 4);
     const int64_t col0 = col - wave;  // first column of the block (uniform)
     {
