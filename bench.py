@@ -475,6 +475,37 @@ def batched_leg(args, B, W, torch):
 # --------------------------------------------------------------------------
 # a13: discrete adjoint against the forward solver and finite differences
 # --------------------------------------------------------------------------
+def adjoint_3d_timing(args, B, W, torch, reps=5):
+    """teno_rhs and teno_rhs_adjoint on the 3D turbulence field of
+    --adjoint-n3d cells per axis (frozen speeds), ms per call (HIP events)."""
+    p3, U3 = W.turbulence_3d(args.adjoint_n3d, seed=0)
+    S3 = B.Solver(p3)
+    U3d = torch.from_numpy(U3).cuda()
+    R3 = S3.rhs(U3d)
+    a3 = S3.alpha.clone()
+    g3 = B.grid(p3)
+    ws3 = torch.empty(B.adjoint_workspace_bytes(g3), dtype=torch.uint8, device="cuda")
+    lam3 = torch.ones_like(U3d)
+    G3 = torch.empty_like(U3d)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(reps):
+            fn()
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    rhs3_ms = timed(lambda: S3.rhs(U3d, alpha_in=a3, out=R3))
+    adj3_ms = timed(lambda: B.teno_rhs_adjoint(g3, U3d, a3, lam3, G3, ws3))
+    del ws3, G3, lam3, R3, U3d
+    return rhs3_ms, adj3_ms
+
+
 def adjoint_leg(args, B, W, torch):
     import numpy as np
     from paper_2003_09145_amd.adjoint import Recorder
@@ -508,21 +539,7 @@ def adjoint_leg(args, B, W, torch):
     adj_ms = timed(lambda: B.teno_rhs_adjoint(rec.g, Ud, alpha, lam, G, rec.ws_adj))
 
     # the same ratio on a 3D field (kernel-bound rather than launch-bound)
-    p3, U3 = W.turbulence_3d(args.adjoint_n3d, seed=0)
-    S3 = B.Solver(p3)
-    U3d = torch.from_numpy(U3).cuda()
-    R3 = S3.rhs(U3d)
-    a3 = S3.alpha.clone()
-    g3 = B.grid(p3)
-    ws3 = torch.empty(B.adjoint_workspace_bytes(g3), dtype=torch.uint8, device="cuda")
-    lam3 = torch.ones_like(U3d)
-    G3 = torch.empty_like(U3d)
-    reps_saved = reps
-    reps = 5
-    rhs3_ms = timed(lambda: S3.rhs(U3d, alpha_in=a3, out=R3))
-    adj3_ms = timed(lambda: B.teno_rhs_adjoint(g3, U3d, a3, lam3, G3, ws3))
-    reps = reps_saved
-    del ws3, G3, lam3, R3, U3d
+    rhs3_ms, adj3_ms = adjoint_3d_timing(args, B, W, torch)
 
     tgt, _, _ = rec.forward(torch.from_numpy(Ut.copy()).cuda(), steps, 0.5)
     rho_star = tgt[0].clone()
@@ -800,6 +817,52 @@ def summarize_trace(d, bench_json=None):
     print("\n".join(lines))
 
 
+ADJ_TRACE_FILE = os.path.join(ROOT, "profiles", "k_adj_chunk_3d_128_kernel_trace.txt")
+
+
+def summarize_adjoint_trace(d, log=None):
+    """profiles/k_adj_chunk_3d_128_kernel_trace.txt from a rocprofv3
+    --kernel-trace --stats run of `bench.py --adjoint-3d-only`
+    (DIR/adj/*kernel_stats.csv) and, if given, that run's JSON line."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "adj", "*kernel_stats.csv"))
+    if not path:
+        raise SystemExit(f"no kernel_stats.csv under {d}/adj")
+    rows = list(csv.DictReader(open(path[0])))
+    lines = [
+        "# rocprofv3 kernel-trace summary: discrete adjoint of the RHS against the RHS,",
+        "# 3D periodic turbulence 128^3, TENO5-LAD, frozen speeds (teno_rhs_adjoint 6 calls,",
+        "# teno_rhs 7; the first timed call of each is a warm-up)",
+        "#",
+        "# command (repository root, after cd /tmp && export TMPDIR=/tmp; $OUT is any output "
+        "directory):",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/adj -o adj -- "
+        "python3 bench.py --adjoint-3d-only",
+        "#   python3 bench.py --summarize-adjoint-trace $OUT [its JSON line]",
+        "# k_adj_chunk: pass A per axis; k_adj_gather: pass B per axis; k_sweep: the",
+        "# forward sweeps of teno_rhs",
+        f"source_sha256: {sources_sha()}",
+        "#",
+        f"{'kernel':58s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}",
+    ]
+    keep = ("k_adj_", "k_sweep", "k_copy_alpha", "k_alpha")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].replace("void ", "").replace("teno::", "").split("(")[0]
+        if not name.startswith(keep):
+            continue
+        lines.append(f"{name[:58]:58s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f}")
+    if log:
+        b = json.loads(open(log).read().strip().splitlines()[-1])["adjoint_3d"]
+        lines += ["#", "# HIP events around 5 calls each in the same run:",
+                  f"#   teno_rhs {b['rhs_ms']:.4f} ms, teno_rhs_adjoint {b['rhs_adjoint_ms']:.4f} ms, "
+                  f"ratio {b['rhs_adjoint_over_rhs']:.3f}"]
+    with open(ADJ_TRACE_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -820,12 +883,18 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DIR", "BENCH_JSON"))
+    ap.add_argument("--adjoint-3d-only", action="store_true",
+                    help="time teno_rhs and teno_rhs_adjoint on the 3D field only (profiling)")
+    ap.add_argument("--summarize-adjoint-trace", nargs="+", metavar=("DIR", "JSON"))
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace[:2])
+        return
+    if args.summarize_adjoint_trace:
+        summarize_adjoint_trace(*args.summarize_adjoint_trace[:2])
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on exactly one GPU (--gpus 1); sharding over several "
@@ -841,6 +910,12 @@ def main():
     from paper_2003_09145_amd import workloads as W
 
     B.lib()
+    if args.adjoint_3d_only:
+        r3, a3 = adjoint_3d_timing(args, B, W, torch)
+        print(json.dumps({"adjoint_3d": {"workload": f"3D turbulence {args.adjoint_n3d}^3",
+                                         "rhs_ms": r3, "rhs_adjoint_ms": a3,
+                                         "rhs_adjoint_over_rhs": a3 / r3}}), flush=True)
+        return
     prob, U, value, ms, roofline, whole = headline(args, B, W, torch)
     out = {
         "metric": METRIC,
