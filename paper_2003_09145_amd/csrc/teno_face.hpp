@@ -228,7 +228,7 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
     // the field-type branches are scalar): project the split fluxes of the
     // stencil on the left eigenvector, reconstruct f^+ and f^-, and add
     // R[:, s] * fhat_s to the face flux.
-#pragma unroll 1
+#pragma unroll
     for (int s = 0; s < NC; ++s) {
         const bool acoustic = (s == 0 || s == NC - 1);
         const bool entropy = (s == 1);
