@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
 #pragma unroll
         for (int kk = 0; kk < ND - 1; ++kk) ut_b[kk] = 0.0;
         uint32_t masks = 0;
-#pragma unroll 1
+#pragma unroll
         for (int s = 0; s < NC; ++s) {
             double Lr[NC];
             left_row<ND>(R, s, Lr);
