@@ -224,10 +224,11 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
 #pragma unroll
     for (int qq = 0; qq < NC; ++qq) Fh[qq] = 0.0;
 
-    // Characteristic fields one at a time (s is uniform across the wave, so
-    // the field-type branches are scalar): project the split fluxes of the
-    // stencil on the left eigenvector, reconstruct f^+ and f^-, and add
-    // R[:, s] * fhat_s to the face flux.
+    // Characteristic fields one at a time, the loop unrolled so that each
+    // field's projection, reconstruction and accumulation is specialized at
+    // compile time: project the split fluxes of the stencil on the left
+    // eigenvector, reconstruct f^+ and f^-, and add R[:, s] * fhat_s to the
+    // face flux.
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const bool acoustic = (s == 0 || s == NC - 1);
