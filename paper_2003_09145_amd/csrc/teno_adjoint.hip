@@ -240,7 +240,7 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         for (int s = 0; s < NC; ++s)
 #pragma unroll
             for (int c = 0; c < NC; ++c) Lb[s][c] = 0.0;
-#pragma unroll 1
+#pragma unroll
         for (int j = 0; j < 6; ++j) {
             const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
             double a[NC], b[NC];
