@@ -229,6 +229,37 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
     __syncthreads();
 
+    // ---- the cell this thread updates ----------------------------------------
+    // Face j of the chunk (j >= 1) updates its left cell from the fluxes at
+    // faces j and j - 1 (COOP: thread t updates column t % W, face t / W).
+    int jj = lane;
+    int64_t blj = bl, phij = phi;
+    bool upd = valid && lane > 0 && phi > 0;
+    const double* fh_c = fhs;
+    int64_t colbase_j = (DIR == 0) ? 0 : colbase;
+    if constexpr (COOP) {
+        jj = (int)(threadIdx.x / W);
+        const int tqj = phi0 + jj;
+        const int wrj = div_by(tqj, A.m1, A.s1);
+        blj = bl0 + wrj;
+        phij = tqj - wrj * (int)np1;
+        upd = F0 + jj < A.ftot && jj > 0 && phij > 0;
+        const int cc = (int)(threadIdx.x % W);
+        fh_c = smem + 24 + (size_t)cc * per_wave;
+        colbase_j = (col0 + cc) * A.col_step;
+    }
+    const int64_t cell = colbase_j + blj * A.line_step + (phij - 1) * A.stride;
+    // the stage input of the fused update is loaded now, so that the face
+    // computation covers the latency (each cell is read and written by its
+    // own thread only, and the stencils read LDS)
+    double u_in[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u_in[c] = 0.0;
+    if (upd && A.rk != 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u_in[c] = A.U[(size_t)c * A.ncell + cell];
+    }
+
     // ---- numerical flux at this lane's face ----------------------------------
     // the digest is wanted or not for the whole launch (a uniform branch); the
     // plain variant carries no digest code at all
@@ -277,37 +308,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 
     // ---- flux difference and epilogue ---------------------------------------
-    // Face j of the chunk (j >= 1) updates its left cell from the fluxes at
-    // faces j and j - 1 (COOP: thread t updates column t % W, face t / W).
-    int jj = lane;
-    int64_t blj = bl, phij = phi;
-    bool upd = valid && lane > 0 && phi > 0;
-    const double* fh_c = fhs;
-    int64_t colbase_j = (DIR == 0) ? 0 : colbase;
-    if constexpr (COOP) {
-        jj = (int)(threadIdx.x / W);
-        const int tqj = phi0 + jj;
-        const int wrj = div_by(tqj, A.m1, A.s1);
-        blj = bl0 + wrj;
-        phij = tqj - wrj * (int)np1;
-        upd = F0 + jj < A.ftot && jj > 0 && phij > 0;
-        const int cc = (int)(threadIdx.x % W);
-        fh_c = smem + 24 + (size_t)cc * per_wave;
-        colbase_j = (col0 + cc) * A.col_step;
-    }
-    // The cell's partial RHS, stage input and u^n are loaded before the
-    // barrier, so that their latency overlaps the wait: each cell is read and
-    // written by its own thread only, and the stencils read a different array.
-    const int64_t cell = colbase_j + blj * A.line_step + (phij - 1) * A.stride;
-    double r_in[NC], u_in[NC], u_n[NC];
+    // The cell's partial RHS and u^n are loaded before the barrier, so that
+    // their latency overlaps the wait.
+    double r_in[NC], u_n[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) r_in[c] = u_in[c] = u_n[c] = 0.0;
+    for (int c = 0; c < NC; ++c) r_in[c] = u_n[c] = 0.0;
     if (upd) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const size_t at = (size_t)c * A.ncell + cell;
             if (A.Rin != nullptr) r_in[c] = A.Rin[at];
-            if (A.rk != 0) u_in[c] = A.U[at];
             if (A.rk >= 2) u_n[c] = A.Un[at];
         }
     }
