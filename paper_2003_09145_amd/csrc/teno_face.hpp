@@ -17,7 +17,7 @@ namespace teno {
 // component order, ghost flip already applied): primitives (u_k = m_k / rho,
 // p = (gamma - 1)(E - ke), H = (E + p) / rho), the flux along DIR (eq 4.7) and
 // its split f+- = (F +- alpha U) / 2 in local order.
-template <int ND, int DIR>
+template <int ND, int DIR, bool MIRROR = false>
 __device__ __forceinline__ void stage_cell(const double* q, double alpha, double gm1,
                                        double* __restrict__ ext, int cap, int idx) {
     constexpr int NC = ND + 2;
@@ -65,7 +65,11 @@ __device__ __forceinline__ void stage_cell(const double* q, double alpha, double
     for (int qq = 0; qq < NC; ++qq) {
         const int g = LO::nat(qq);
         ext[(size_t)qq * cap + idx] = 0.5 * __builtin_fma(alpha, q[g], Fl[g]);
-        ext[(size_t)(NC + qq) * cap + idx] = 0.5 * __builtin_fma(-alpha, q[g], Fl[g]);
+        // MIRROR: the f- rows hold the cells in reverse (column cap - 1 -
+        // idx), so that its mirrored stencil i+3 .. i-1 reads ascending
+        // columns too
+        ext[(size_t)(NC + qq) * cap + (MIRROR ? cap - 1 - idx : idx)] =
+            0.5 * __builtin_fma(-alpha, q[g], Fl[g]);
     }
     ext[(size_t)(2 * NC) * cap + idx] = srho;
 #pragma unroll
@@ -172,27 +176,31 @@ __device__ __forceinline__ void left_row(const FaceRoe<ND>& R, int s, double (&L
 // sg = 1: f- on the mirrored stencil i+3 .. i-1) projected on the left
 // eigenvector row Lr and reconstructed at the face (eq 2.3-2.15); *code
 // receives the decision code (cutoff mask in bits 5..7).
-template <int ND, bool A5>
+template <int ND, bool A5, bool MIRROR = false>
 __device__ __forceinline__ double char_rec(const double* __restrict__ ext, int cap, int o, int s,
                                            int sg, const double (&Lr)[ND + 2],
                                            const SchemeParams& sch, const DecisionConsts& dk,
                                            const double* __restrict__ omega, uint32_t* code) {
     constexpr int NC = ND + 2;
     const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-    const double* fb = ext + (size_t)(sg ? NC : 0) * cap + o;
+    // f+ on cells o .. o+4 (point j at column o + j); f- on o+5 .. o+1: at
+    // column o + 5 - j, or (MIRROR, reversed rows) at cap - 6 - o + j
+    const bool asc = !sg || MIRROR;
+    const double* fb = !sg ? ext + o
+                           : ext + (size_t)NC * cap + (MIRROR ? cap - 6 - o : o);
     // the field-type test outside the stencil loop, so that the five points'
     // reads form one block the scheduler can issue ahead of their products
     double v[5];
     if (shear) {  // the unit entry: a plain add, as the oracle's fma by 1
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            const int cj = sg ? 5 - j : j;
+            const int cj = asc ? j : 5 - j;
             v[j] = Lr[0] * fb[cj] + fb[(size_t)s * cap + cj];
         }
     } else {
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            const int cj = sg ? 5 - j : j;
+            const int cj = asc ? j : 5 - j;
             double acc = Lr[0] * fb[cj];
 #pragma unroll
             for (int qq = 1; qq < NC; ++qq)
@@ -210,7 +218,7 @@ __device__ __forceinline__ double char_rec(const double* __restrict__ ext, int c
 // Fnat receives the flux in natural
 // component order; o8 (nullable) receives the 2 NC decision codes and masks
 // (nullable, initialised by the caller) the 2 NC cutoff masks, 3 bits each.
-template <int ND, int DIR, bool A5>
+template <int ND, int DIR, bool A5, bool MIRROR = false>
 __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int cap, int o,
                                       double gm1, const SchemeParams& sch,
                                       const DecisionConsts& dk,
@@ -240,7 +248,7 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ ext, int ca
         for (int sg = 0; sg < 2; ++sg) {
             __asm__ __volatile__("" ::: "memory");
             uint32_t code;
-            const double r = char_rec<ND, A5>(ext, cap, o, s, sg, Lr, sch, dk, omega, &code);
+            const double r = char_rec<ND, A5, MIRROR>(ext, cap, o, s, sg, Lr, sch, dk, omega, &code);
             if (o8 != nullptr) o8[2 * s + sg] = (uint8_t)code;
             if (masks != nullptr) *masks |= (code >> 5) << (3 * (2 * s + sg));
             fh = sg ? fh + r : r;

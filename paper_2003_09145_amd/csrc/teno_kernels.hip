@@ -140,6 +140,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     // 6 cells; the block stages their union once, in one shared buffer, and
     // each wave reads its faces' stencils at its own offset in it.
     constexpr bool XCOOP = (DIR == 0) && (CAPC > 74);
+    // y and z sweeps store the f- rows reversed (measured faster there, and
+    // slower along x)
+    constexpr bool MIRROR = DIR != 0;
     double* omega = smem;  // 24 doubles: eq 2.15 weights per cutoff mask
     const int per_wave = XCOOP ? 64 * NC : ((cap * NV > 64 * NC) ? cap * NV : 64 * NC);
     double* ext = XCOOP ? smem + 24 : smem + 24 + (size_t)wave * per_wave;
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int cur = idx;
         idx += kStep;
         if (idx < count) load_cell(idx, qn);
-        stage_cell<ND, DIR>(q, alpha, gm1, ext_c, cap, cur);
+        stage_cell<ND, DIR, MIRROR>(q, alpha, gm1, ext_c, cap, cur);
     }
     }
     __syncthreads();
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
             o8 = A.dump + (gline * np1 + phi) * (2 * NC);
         }
         uint32_t masks = 0;
-        face_flux<ND, DIR, A5>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
+        face_flux<ND, DIR, A5, MIRROR>(ext, cap, o, gm1, A.sch, A.dk, omega, o8, Fh,
                            want_digest ? &masks : nullptr);
         if constexpr (!XCOOP) {
 #pragma unroll
