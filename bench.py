@@ -115,9 +115,9 @@ def sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-# waves per block of the fixed-stride sweeps on a 256^3 grid: x one-wave
-# blocks, y four neighbouring columns, z eight
-SWEEP_WAVES = {0: 1, 1: 4, 2: 8}
+# waves per block of the fixed-stride sweeps on a 256^3 grid: x four waves on
+# consecutive chunks of one line, y four neighbouring columns, z eight
+SWEEP_WAVES = {0: 4, 1: 4, 2: 8}
 
 
 def load_traffic(kernel: str):
