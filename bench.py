@@ -120,6 +120,13 @@ def sources_sha() -> str:
 SWEEP_WAVES = {0: 4, 1: 4, 2: 8}
 
 
+def match_kernel(names, kernel: str):
+    """The entries of `names` that are `kernel` or an instantiation that
+    extends its template arguments (k_sweep<3,2,8,false> matches
+    k_sweep<3,2,8,false,74,false>)."""
+    return [k for k in names if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
+
+
 def load_traffic(kernel: str):
     """Counter-measured HBM bytes per launch of `kernel` from the committed
     summary, or None when the sweep sources changed since it was taken."""
@@ -133,7 +140,7 @@ def load_traffic(kernel: str):
             name, rest = line[len("kernel "):].split(":", 1)
             kv = dict(x.strip().split("=") for x in rest.split(","))
             vals[name.strip()] = kv
-    names = [k for k in vals if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
+    names = match_kernel(vals, kernel)
     if sha != sources_sha() or len(names) != 1:
         return None
     kv = vals[names[0]]

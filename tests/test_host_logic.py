@@ -1,6 +1,7 @@
-"""Host-side integer logic of the kernels, checked on the CPU: the
-multiply-and-shift constants that replace per-lane divisions by the line
-length (n + 1, n + 6) and the column count in the sweep kernels."""
+"""Host-side logic checked on the CPU: the multiply-and-shift constants that
+replace per-lane divisions by the line length (n + 1, n + 6) and the column
+count in the sweep kernels, the exactness of the fused power-of-two products,
+and the kernel names under which bench.py looks up the sweeps' counters."""
 import os
 import subprocess
 
@@ -96,3 +97,18 @@ def test_power_of_two_products_fuse_exactly(tmp_path):
                     str(src)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
+
+
+def test_bench_sweep_names_resolve_in_counter_summary():
+    """The kernel name bench.py derives for each axis's 3D sweep picks out
+    exactly one kernel of the committed counter summary (else its traffic
+    figure would silently read as missing)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import bench
+    names = [line[len("kernel "):].split(":", 1)[0].strip()
+             for line in open(bench.TRAFFIC_FILE) if line.startswith("kernel ")]
+    assert len(names) == 3
+    for d in range(3):
+        kname = f"k_sweep<3,{d},{bench.SWEEP_WAVES[d]},false>"
+        assert len(bench.match_kernel(names, kname)) == 1, (kname, names)
