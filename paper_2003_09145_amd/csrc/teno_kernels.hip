@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ U, int
          i += (int64_t)gridDim.x * blockDim.x) {
         double q[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = U[c * ncell + i];
+        for (int c = 0; c < NC; ++c) q[c] = __builtin_nontemporal_load(&U[c * ncell + i]);
         const double rho = q[0];
         double u[ND];
         const double rrho = rcp_nr(rho);
