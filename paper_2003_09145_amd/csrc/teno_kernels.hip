@@ -123,11 +123,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     // variants' column split scalar (along x it only costs registers)
     const int wave = DIR != 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    // The y sweep walks its tiles from the end, so that it first reads the
-    // partial RHS and state the x sweep touched last, while they are still
-    // in the memory-side cache; z then walks forward again.
+    // The y and z sweeps walk their tiles from the end: y then first reads
+    // the partial RHS and state that the x sweep touched last, while they
+    // are still in the memory-side cache (measured: y and z each about 1%
+    // faster than walking forward; x is not helped)
     const int64_t lb0 = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int64_t lb = DIR == 1 ? (int64_t)gridDim.x - 1 - lb0 : lb0;
+    const int64_t lb = DIR != 0 ? (int64_t)gridDim.x - 1 - lb0 : lb0;
     const int64_t chunk = lb * W + wave;
     const bool wave_ok = chunk < A.nchunks;
     const int n = A.n;
