@@ -26,6 +26,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "teno_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with -DORACLE_LITERAL: every formula as its plain
+# product-then-sum, no fused multiply-add (see the file header)
+_LIB_LITERAL = os.path.join(_HERE, "liboracle_literal.so")
 
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
@@ -59,24 +62,27 @@ class OrParams(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle library with g++: no fast-math and no FMA contraction;
-    the explicit fused multiply-adds use the hardware instruction (-mfma)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-mfma", "-fopenmp",
-               "-fPIC", "-shared", "-std=c++17", "-o", _LIB + ".tmp", _SRC]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile both oracle libraries with g++: no fast-math and no FMA
+    contraction; the explicit fused multiply-adds of the default build use the
+    hardware instruction (-mfma), the literal build has none."""
+    for out, extra in ((_LIB, []), (_LIB_LITERAL, ["-DORACLE_LITERAL"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-mfma", "-fopenmp",
+                   "-fPIC", "-shared", "-std=c++17", *extra, "-o", out + ".tmp", _SRC]
+            subprocess.run(cmd, check=True)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(literal: bool = False):
+    """The oracle library; literal=True loads the FMA-free build."""
+    key = bool(literal)
+    if key not in _libs:
         build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_LITERAL if key else _LIB)
         P = ctypes.POINTER(OrParams)
         dp = ctypes.POINTER(ctypes.c_double)
         u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -104,8 +110,15 @@ def lib():
         L.or_advect_run.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, dp]
         L.or_advect_run.restype = ctypes.c_int64
-        _lib = L
-    return _lib
+        L.or_run_jvp_batch.argtypes = [P, dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp]
+        L.or_run_jvp_batch.restype = ctypes.c_int
+        L.or_rhs_fluxabs.argtypes = [P, dp, dp, dp]
+        L.or_rhs_fluxabs.restype = ctypes.c_int
+        L.or_literal.argtypes = []
+        L.or_literal.restype = ctypes.c_int
+        assert L.or_literal() == int(key)
+        _libs[key] = L
+    return _libs[key]
 
 
 def _get(prob, key, default=None):
@@ -177,7 +190,7 @@ def _shape(p: OrParams):
     return (p.ndim + 2, p.n[2], p.n[1], p.n[0])
 
 
-def rec(v, prob=None, trace: bool = False):
+def rec(v, prob=None, trace: bool = False, literal=False):
     """One scalar TENO reconstruction of (f_{i-2}, ..., f_{i+2}).
 
     Returns (fhat, m, mask) or, with trace=True, also a dict of the
@@ -187,7 +200,7 @@ def rec(v, prob=None, trace: bool = False):
     m = ctypes.c_int32()
     mask = ctypes.c_int32()
     tr = np.zeros(17)
-    f = lib().or_rec(ctypes.byref(p), _dp(v), ctypes.byref(m), ctypes.byref(mask), _dp(tr))
+    f = lib(literal).or_rec(ctypes.byref(p), _dp(v), ctypes.byref(m), ctypes.byref(mask), _dp(tr))
     if not trace:
         return f, m.value, mask.value
     d = {"beta": tr[0:3].copy(), "tau": tr[3], "t": tr[4:7].copy(), "gamma": tr[7:10].copy(),
@@ -221,7 +234,7 @@ def dump_size(prob) -> int:
     return sum((ncell // p.n[d]) * (p.n[d] + 1) * 2 * nc for d in range(p.ndim))
 
 
-def rhs(prob, U, alpha3=None, dump: bool = False):
+def rhs(prob, U, alpha3=None, dump: bool = False, literal=False):
     """dU/dt = L(U) (eq 2.2 per direction).  alpha3 freezes the LF speeds.
 
     Returns dUdt, or (dUdt, decisions) with dump=True."""
@@ -231,12 +244,23 @@ def rhs(prob, U, alpha3=None, dump: bool = False):
     out = np.zeros_like(U)
     a = None if alpha3 is None else _f64(alpha3)
     dmp = np.zeros(dump_size(prob), dtype=np.uint8) if dump else None
-    lib().or_rhs(ctypes.byref(p), _dp(U), None if a is None else _dp(a), _dp(out),
+    lib(literal).or_rhs(ctypes.byref(p), _dp(U), None if a is None else _dp(a), _dp(out),
                  None if dmp is None else dmp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return (out, dmp) if dump else out
 
 
-def rhs_cells(prob, U, alpha3, cells, dump: bool = False):
+def rhs_flux_abs(prob, U, literal=False):
+    """(dUdt, S) with S[q] = sum over axes d and faces f of |F^_{f,q}| / dx_d,
+    the magnitude of the face-flux terms (for rounding bounds)."""
+    p = params(prob)
+    U = _f64(U)
+    out = np.zeros_like(U)
+    S = np.zeros(5)
+    lib(literal).or_rhs_fluxabs(ctypes.byref(p), _dp(U), _dp(out), _dp(S))
+    return out, S[:p.ndim + 2].copy()
+
+
+def rhs_cells(prob, U, alpha3, cells, dump: bool = False, literal=False):
     """RHS at selected flat cell indices; returns (ncell, nc) [and decisions
     of shape (ncell, ndim, 2 faces, 2*nc), faces i-1/2 then i+1/2]."""
     p = params(prob)
@@ -245,24 +269,24 @@ def rhs_cells(prob, U, alpha3, cells, dump: bool = False):
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.zeros((len(cells), nc))
     dmp = np.zeros((len(cells), p.ndim, 2, 2 * nc), dtype=np.uint8) if dump else None
-    lib().or_rhs_cells(ctypes.byref(p), _dp(U), _dp(_f64(alpha3)), len(cells),
+    lib(literal).or_rhs_cells(ctypes.byref(p), _dp(U), _dp(_f64(alpha3)), len(cells),
                        cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out),
                        None if dmp is None else dmp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return (out, dmp) if dump else out
 
 
-def rhs_jvp(prob, U, V, alpha3):
+def rhs_jvp(prob, U, V, alpha3, literal=False):
     """(L(U), dL/dU . V) with alpha and the cutoff decisions frozen."""
     p = params(prob)
     U = _f64(U)
     V = _f64(V)
     out = np.zeros_like(U)
     jv = np.zeros_like(U)
-    lib().or_rhs_jvp(ctypes.byref(p), _dp(U), _dp(V), _dp(_f64(alpha3)), _dp(out), _dp(jv))
+    lib(literal).or_rhs_jvp(ctypes.byref(p), _dp(U), _dp(V), _dp(_f64(alpha3)), _dp(out), _dp(jv))
     return out, jv
 
 
-def step(prob, U, cfl, t, t_end, replay=None):
+def step(prob, U, cfl, t, t_end, replay=None, literal=False):
     """One SSP-RK3 step (eq 4.1-4.3) on a copy of U.
 
     replay = (dt, alpha9) freezes dt and the per-stage LF speeds.
@@ -278,18 +302,18 @@ def step(prob, U, cfl, t, t_end, replay=None):
         dt = ctypes.c_double(float(replay[0]))
         a9 = _f64(replay[1]).reshape(9).copy()
         rp = 1
-    st = lib().or_step(ctypes.byref(p), _dp(U), float(cfl), ctypes.byref(tt), float(t_end),
+    st = lib(literal).or_step(ctypes.byref(p), _dp(U), float(cfl), ctypes.byref(tt), float(t_end),
                        rp, ctypes.byref(dt), _dp(a9))
     return U, tt.value, dt.value, a9.reshape(3, 3), st
 
 
-def run(prob, U, cfl, t_end=np.inf, nsteps=None, record=False):
+def run(prob, U, cfl, t_end=np.inf, nsteps=None, record=False, literal=False):
     """Advance with RK3 until t_end or nsteps.  Returns (U, t, steps[, dts, alphas])."""
     t = 0.0
     k = 0
     dts, als = [], []
     while t < t_end and (nsteps is None or k < nsteps):
-        U, t, dt, a9, st = step(prob, U, cfl, t, t_end)
+        U, t, dt, a9, st = step(prob, U, cfl, t, t_end, literal=literal)
         if st != 0:
             raise FloatingPointError(f"non-physical state at step {k}")
         dts.append(dt)
@@ -300,30 +324,44 @@ def run(prob, U, cfl, t_end=np.inf, nsteps=None, record=False):
     return U, t, k
 
 
-def run_jvp(prob, U, V, dts, alphas):
+def run_jvp(prob, U, V, dts, alphas, literal=False):
     """Forward-mode derivative through replayed RK3 steps."""
     p = params(prob)
     U = _f64(U).copy()
     V = _f64(V).copy()
     dts = _f64(dts)
     alphas = _f64(alphas).reshape(-1)
-    lib().or_run_jvp(ctypes.byref(p), _dp(U), _dp(V), len(dts), _dp(dts), _dp(alphas))
+    lib(literal).or_run_jvp(ctypes.byref(p), _dp(U), _dp(V), len(dts), _dp(dts), _dp(alphas))
     return U, V
 
 
-def advect_rhs(u, dx, scheme="lad", **kw):
+def run_jvp_batch(prob, U, Vs, dts, alphas, literal=False):
+    """Forward-mode derivatives of the same replayed run along several
+    tangents Vs (shape (k,) + U.shape), in parallel; returns the k final
+    tangents."""
+    p = params(prob)
+    U = _f64(U)
+    Vs = _f64(Vs).copy()
+    dts = _f64(dts)
+    alphas = _f64(alphas).reshape(-1)
+    lib(literal).or_run_jvp_batch(ctypes.byref(p), _dp(U), _dp(Vs), Vs.shape[0], len(dts),
+                                  _dp(dts), _dp(alphas))
+    return Vs
+
+
+def advect_rhs(u, dx, scheme="lad", literal=False, **kw):
     prob = dict(ndim=1, n=[len(u)], dx=[dx], bc="periodic", scheme=scheme, **kw)
     p = params(prob)
     u = _f64(u)
     out = np.zeros_like(u)
-    lib().or_advect_rhs(ctypes.byref(p), len(u), float(dx), _dp(u), _dp(out))
+    lib(literal).or_advect_rhs(ctypes.byref(p), len(u), float(dx), _dp(u), _dp(out))
     return out
 
 
-def advect_run(u, dx, dt, t_end, scheme="lad", **kw):
+def advect_run(u, dx, dt, t_end, scheme="lad", literal=False, **kw):
     """Linear advection u_t + u_x = 0 (Sec. 4.1), periodic, RK3 with fixed dt."""
     prob = dict(ndim=1, n=[len(u)], dx=[dx], bc="periodic", scheme=scheme, **kw)
     p = params(prob)
     u = _f64(u).copy()
-    steps = lib().or_advect_run(ctypes.byref(p), len(u), float(dx), float(dt), float(t_end), _dp(u))
+    steps = lib(literal).or_advect_run(ctypes.byref(p), len(u), float(dx), float(dt), float(t_end), _dp(u))
     return u, steps

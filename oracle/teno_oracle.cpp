@@ -37,12 +37,23 @@
  *    t + dt/2);
  *  - the gravity source of the Rayleigh-Taylor problem is added after the
  *    flux differences;
- *  - the sums of products of the reconstruction (smoothness indicators
- *    eq 2.9-2.11, candidate fluxes eq 2.4-2.6, their weighted sum eq 2.7),
- *    of the global Lax-Friedrichs split (F +- alpha U) / 2, of the
- *    characteristic projection onto the left eigenvectors and of the
- *    back-projection R f^ are evaluated with fused multiply-adds, in the
- *    order written below.
+ *  - rounding of the sums of products (the paper fixes none).  The file
+ *    builds in two modes:
+ *      default: the smoothness indicators (eq 2.9-2.11), candidate fluxes
+ *        (eq 2.4-2.6), their weighted sum (eq 2.7), the global
+ *        Lax-Friedrichs split (F +- alpha U) / 2, the characteristic
+ *        projection onto the left eigenvectors and the back-projection R f^
+ *        use fused multiply-adds, in the order written below;
+ *      ORACLE_LITERAL: no fused operation anywhere.  Each formula is the
+ *        plain product-then-sum of its printed form, left to right:
+ *        beta_0 = 13/12 (a - 2b + c)^2 + 1/4 (a - 4b + 3c)^2,
+ *        f_0 = (1/3 a - 7/6 b) + 11/6 c, f_1 = (-1/6 b + 5/6 c) + 1/3 d,
+ *        f_2 = (1/3 c + 5/6 d) - 1/6 e, f^ = (w_0 f_0 + w_1 f_1) + w_2 f_2;
+ *        the projection first (w_j = L U_j, g_j = L F_j, summed over the
+ *        components in order), then the split v+- = (g_j +- alpha w_j) / 2;
+ *        F^ = R (f^+ + f^-) summed over the fields in order.
+ *    Both modes are the same method; they differ only in rounding, which is
+ *    what a comparison between them measures.
  */
 #include <cmath>
 #include <cstdint>
@@ -162,16 +173,28 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
                      double e, DecisionTrace* tr) {
     /* Jiang-Shu smoothness indicators, eq 2.9-2.11, on (f_{i-2} .. f_{i+2}) =
      * (a, b, c, d, e). */
+    double beta[3];
+#ifdef ORACLE_LITERAL
+    double s01 = (a - 2.0 * b) + c;
+    double s02 = (a - 4.0 * b) + 3.0 * c;
+    double s11 = (b - 2.0 * c) + d;
+    double s12 = b - d;
+    double s21 = (c - 2.0 * d) + e;
+    double s22 = (3.0 * c - 4.0 * d) + e;
+    beta[0] = K13_12 * (s01 * s01) + K1_4 * (s02 * s02);
+    beta[1] = K13_12 * (s11 * s11) + K1_4 * (s12 * s12);
+    beta[2] = K13_12 * (s21 * s21) + K1_4 * (s22 * s22);
+#else
     double s01 = (a - 2.0 * b) + c;
     double s02 = fmadd(3.0, c, a - 4.0 * b);
     double s11 = (b - 2.0 * c) + d;
     double s12 = b - d;
     double s21 = (c - 2.0 * d) + e;
     double s22 = fmadd(3.0, c, e - 4.0 * d);
-    double beta[3];
     beta[0] = fmadd(K13_12 * s01, s01, K1_4 * (s02 * s02));
     beta[1] = fmadd(K13_12 * s11, s11, K1_4 * (s12 * s12));
     beta[2] = fmadd(K13_12 * s21, s21, K1_4 * (s22 * s22));
+#endif
     /* Global smoothness indicator tau_5 = |beta_2 - beta_0|, eq 2.12. */
     double tau = std::fabs(beta[2] - beta[0]);
     /* chi-tilde_k = tau / (beta_k + eps) (eq 3.2), which is also the ratio
@@ -267,15 +290,25 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
  * eq 2.15, combination eq 2.7.  Linear in (a..e) once the mask is fixed. */
 template <class T>
 T teno_flux(int mask, T a, T b, T c, T d, T e) {
+#ifdef ORACLE_LITERAL
+    T f0 = (T1_3 * a - T7_6 * b) + T11_6 * c;
+    T f1 = (-T1_6 * b + T5_6 * c) + T1_3 * d;
+    T f2 = (T1_3 * c + T5_6 * d) - T1_6 * e;
+#else
     T f0 = fmadd(T11_6, c, fmadd(T1_3, a, -T7_6 * b));
     T f1 = fmadd(T1_3, d, fmadd(-T1_6, b, T5_6 * c));
     T f2 = fmadd(-T1_6, e, fmadd(T1_3, c, T5_6 * d));
+#endif
     double dl[3];
     for (int k = 0; k < 3; ++k) dl[k] = (double)((mask >> k) & 1);
     double D = (dl[0] * C_LIN[0] + dl[1] * C_LIN[1]) + dl[2] * C_LIN[2];
     double w[3];
     for (int k = 0; k < 3; ++k) w[k] = (dl[k] * C_LIN[k]) / D;
+#ifdef ORACLE_LITERAL
+    return (w[0] * f0 + w[1] * f1) + w[2] * f2;
+#else
     return fmadd(w[2], f2, fmadd(w[0], f0, w[1] * f1));
+#endif
 }
 
 template <class T>
@@ -486,26 +519,46 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
     int nd = P.ndim, nc = nd + 2;
     int perm[5];
     local_perm(nd, d, perm);
-    /* Global Lax-Friedrichs splitting of the cell fluxes:
-     * f^{+-}_j = 1/2 (F_j +- alpha U_j), taken to local order. */
-    T fp[6][5], fm[6][5];
+    /* Cell fluxes F_j and states U_j of the stencil in local order. */
+    T Uloc[6][5], Floc[6][5];
     for (int j = 0; j < 6; ++j) {
         Prim<T> w = primitives(P, st[j]);
         T F[5];
         euler_flux(P, d, st[j], w, F);
         for (int q = 0; q < nc; ++q) {
-            int g = perm[q];
-            fp[j][q] = 0.5 * fmadd(alpha, st[j][g], F[g]);
-            fm[j][q] = 0.5 * fmadd(-alpha, st[j][g], F[g]);
+            Uloc[j][q] = st[j][perm[q]];
+            Floc[j][q] = F[perm[q]];
         }
     }
+#ifndef ORACLE_LITERAL
+    /* Global Lax-Friedrichs splitting of the cell fluxes first:
+     * f^{+-}_j = 1/2 (F_j +- alpha U_j). */
+    T fp[6][5], fm[6][5];
+    for (int j = 0; j < 6; ++j)
+        for (int q = 0; q < nc; ++q) {
+            fp[j][q] = 0.5 * fmadd(alpha, Uloc[j][q], Floc[j][q]);
+            fm[j][q] = 0.5 * fmadd(-alpha, Uloc[j][q], Floc[j][q]);
+        }
+#endif
     /* Characteristic projection at the Roe state of cells i and i+1. */
     T Lm[5][5], Rm[5][5];
     roe_eigen(P, d, st[2], st[3], Lm, Rm);
     T fh[5];
     for (int s = 0; s < nc; ++s) {
+        /* Projected split fluxes v^{+-}_j = l_s . (F_j +- alpha U_j) / 2. */
         T vp[6], vm[6];
         for (int j = 0; j < 6; ++j) {
+#ifdef ORACLE_LITERAL
+            /* projection first (w_j = l_s . U_j, g_j = l_s . F_j), then the split */
+            T wj = Lm[s][0] * Uloc[j][0];
+            T gj = Lm[s][0] * Floc[j][0];
+            for (int q = 1; q < nc; ++q) {
+                wj = wj + Lm[s][q] * Uloc[j][q];
+                gj = gj + Lm[s][q] * Floc[j][q];
+            }
+            vp[j] = 0.5 * (gj + alpha * wj);
+            vm[j] = 0.5 * (gj - alpha * wj);
+#else
             T ap = Lm[s][0] * fp[j][0];
             T am = Lm[s][0] * fm[j][0];
             for (int q = 1; q < nc; ++q) {
@@ -514,6 +567,7 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
             }
             vp[j] = ap;
             vm[j] = am;
+#endif
         }
         Decision dp, dm;
         /* f^+ on cells i-2..i+2; f^- on the mirrored stencil i+3..i-1. */
@@ -528,7 +582,11 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
     /* Back to conserved variables: F^ = R f^. */
     for (int q = 0; q < nc; ++q) {
         T acc = Rm[q][0] * fh[0];
+#ifdef ORACLE_LITERAL
+        for (int s = 1; s < nc; ++s) acc = acc + Rm[q][s] * fh[s];
+#else
         for (int s = 1; s < nc; ++s) acc = fmadd(Rm[q][s], fh[s], acc);
+#endif
         Fhat[perm[q]] = acc;
     }
 }
@@ -578,7 +636,7 @@ void lf_alpha(const OrParams& P, const double* U, double alpha[3], int* status) 
 /* ------------------------------------------------------------------------ */
 template <class T>
 void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
-              uint8_t* dump, double t) {
+              uint8_t* dump, double t, double* flux_abs = nullptr) {
     int nd = P.ndim, nc = nd + 2;
     int64_t N = ncells(P);
     for (int64_t i = 0; i < (int64_t)nc * N; ++i) out[i] = from_double<T>(0.0);
@@ -615,6 +673,16 @@ void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
                     T diff = fl[(size_t)(i + 1) * 5 + q] - fl[(size_t)i * 5 + q];
                     out[q * N + ci] = out[q * N + ci] - diff / dxd;
                 }
+            }
+            if (flux_abs) {
+                /* sum over the line's faces of |F^| / dx (magnitudes for
+                 * rounding bounds; not part of the method) */
+                double loc[5] = {0, 0, 0, 0, 0};
+                for (int phi = 0; phi <= n; ++phi)
+                    for (int q = 0; q < nc; ++q)
+                        loc[q] += std::fabs(val(fl[(size_t)phi * 5 + q])) / dxd;
+#pragma omp critical
+                for (int q = 0; q < nc; ++q) flux_abs[q] += loc[q];
             }
         }
         dump_off += L * (int64_t)(n + 1) * 2 * nc;
@@ -702,6 +770,15 @@ extern "C" {
 
 int or_version(void) { return 1; }
 
+/* 1 for the ORACLE_LITERAL build (no fused multiply-adds), else 0. */
+int or_literal(void) {
+#ifdef ORACLE_LITERAL
+    return 1;
+#else
+    return 0;
+#endif
+}
+
 /* Scalar reconstruction with its intermediate values.  v[5] = (f_{i-2}..f_{i+2}).
  * out9 = beta0..2, tau, x, theta, ct, chi0, chi1 ... (see below). */
 double or_rec(const OrParams* P, const double* v, int32_t* m, int32_t* mask,
@@ -756,6 +833,18 @@ int or_rhs(const OrParams* P, const double* U, const double* alpha3,
         a[2] = alpha3[2];
     }
     rhs_impl<double>(*P, U, a, dUdt, dump, P->time);
+    return st;
+}
+
+/* dUdt = L(U) as or_rhs, and flux_abs[q] = sum over axes d and faces f of
+ * |F^_f,q| / dx_d (the magnitudes behind the rounding of the flux
+ * differences, for conservation bounds). */
+int or_rhs_fluxabs(const OrParams* P, const double* U, double* dUdt, double* flux_abs) {
+    double a[3];
+    int st = 0;
+    lf_alpha(*P, U, a, &st);
+    for (int q = 0; q < 5; ++q) flux_abs[q] = 0.0;
+    rhs_impl<double>(*P, U, a, dUdt, nullptr, P->time, flux_abs);
     return st;
 }
 
@@ -854,6 +943,20 @@ int or_run_jvp(const OrParams* P, double* U, double* V, int64_t nsteps,
     for (int64_t i = 0; i < tot; ++i) {
         U[i] = X[(size_t)i].v;
         V[i] = X[(size_t)i].d;
+    }
+    return 0;
+}
+
+/* nvec independent forward-mode derivatives of the same replayed run: the
+ * tangents V[k] (k < nvec, each ncell * nc doubles) are advanced in place
+ * from the common start U, one OpenMP thread per tangent. */
+int or_run_jvp_batch(const OrParams* P, const double* U, double* V, int64_t nvec,
+                     int64_t nsteps, const double* dts, const double* alphas) {
+    int64_t tot = ncells(*P) * (P->ndim + 2);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nvec; ++k) {
+        std::vector<double> Uk(U, U + tot);
+        or_run_jvp(P, Uk.data(), V + k * tot, nsteps, dts, alphas);
     }
     return 0;
 }
