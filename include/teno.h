@@ -217,11 +217,14 @@ int teno_sweep(const teno_grid* g, int32_t axis, const double* U_dev,
  * reciprocal-based routine of the hot loops, s[i] = sqrt(a[i]) -- all
  * correctly rounded (IEEE-754 binary64, round to nearest even) whenever
  * operands and results lie in [2^-900, 2^900] in magnitude -- and r[i] = the
- * approximate reciprocal of b[i] used by the decision fast path.  All
- * pointers are device pointers of n doubles. */
+ * approximate reciprocal of b[i] used by the decision fast path.  For
+ * comparison, qplain[i] and splain[i] (both nullable) receive the compiler's
+ * own a[i] / b[i] and sqrt(a[i]) with no correction, the operations the
+ * correctly rounded routines replace.  All pointers are device pointers of
+ * n doubles. */
 int teno_selftest_arith(const double* a_dev, const double* b_dev, double* q_dev,
-                        double* q2_dev, double* s_dev, double* r_dev, int64_t n,
-                        void* stream);
+                        double* q2_dev, double* s_dev, double* r_dev,
+                        double* qplain_dev, double* splain_dev, int64_t n, void* stream);
 
 /* One SSP-RK3 step of eq 4.1-4.3, in place on U_dev:
  *   u1 = u + dt L(u);  u2 = 3/4 u + 1/4 u1 + 1/4 dt L(u1);

@@ -128,7 +128,7 @@ def lib():
         L.teno_rhs_debug.restype = ctypes.c_int
         L.teno_sweep.argtypes = [G, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.teno_sweep.restype = ctypes.c_int
-        L.teno_selftest_arith.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+        L.teno_selftest_arith.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
         L.teno_selftest_arith.restype = ctypes.c_int
         L.teno_step.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_step.restype = ctypes.c_int
@@ -299,14 +299,17 @@ def teno_sweep(g, axis, U, Rout, alpha, Rin=None, stream=None):
                             _ptr(alpha), _stream(stream)), "teno_sweep")
 
 
-def selftest_arith(a, b, stream=None):
+def selftest_arith(a, b, stream=None, plain=False):
     """(a / b, a / b via the reciprocal route, sqrt(a), approximate 1 / b)
-    computed by the device."""
+    computed by the device; with plain=True also the compiler's uncorrected
+    a / b and sqrt(a)."""
     import torch
     q, q2, s, r = (torch.empty_like(a) for _ in range(4))
+    qp, sp = (torch.empty_like(a), torch.empty_like(a)) if plain else (None, None)
     _check(lib().teno_selftest_arith(_ptr(a), _ptr(b), _ptr(q), _ptr(q2), _ptr(s), _ptr(r),
-                                     a.numel(), _stream(stream)), "teno_selftest_arith")
-    return q, q2, s, r
+                                     _ptr(qp), _ptr(sp), a.numel(), _stream(stream)),
+           "teno_selftest_arith")
+    return (q, q2, s, r, qp, sp) if plain else (q, q2, s, r)
 
 
 def teno_step(g, U, ctrl, ws, stream=None):

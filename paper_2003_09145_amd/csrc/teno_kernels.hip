@@ -575,13 +575,15 @@ __global__ void k_ctrl_digest(teno_ctrl* ctrl, int enable) {
 // Arithmetic self-test: the device's correctly rounded division and square
 // root and the approximate reciprocal used by the decision fast path.
 __global__ void k_selftest_arith(const double* a, const double* b, double* q, double* q2,
-                                 double* s, double* r, int64_t n) {
+                                 double* s, double* r, double* qp, double* sp, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
         q[i] = cr_div(a[i], b[i]);
         q2[i] = cr_div_r(a[i], b[i], rcp_nr(b[i]));
         s[i] = cr_sqrt(a[i]);
         r[i] = rcp_nr(b[i]);
+        if (qp != nullptr) qp[i] = a[i] / b[i];
+        if (sp != nullptr) sp[i] = sqrt(a[i]);
     }
 }
 
@@ -842,14 +844,14 @@ int teno_rhs_debug(const teno_grid* g, const double* U, double* dUdt, const doub
 }
 
 int teno_selftest_arith(const double* a, const double* b, double* q, double* q2, double* s,
-                        double* r, int64_t n, void* stream) {
+                        double* r, double* qp, double* sp, int64_t n, void* stream) {
     if (n < 0 || (n > 0 && (a == nullptr || b == nullptr || q == nullptr || q2 == nullptr ||
                             s == nullptr || r == nullptr)))
         return TENO_ERR_ARG;
     if (n == 0) return TENO_OK;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_selftest_arith, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, a, b, q, q2, s, r, n);
+                       (hipStream_t)stream, a, b, q, q2, s, r, qp, sp, n);
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_ERR_DEVICE;
 }
 

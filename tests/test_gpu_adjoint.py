@@ -172,13 +172,60 @@ def test_trajectory_gradient_and_checkpoint_invariance(torch, B, orc):
         assert rel <= 1e-10
 
 
+def test_gradient_400_steps_against_forward_mode(torch, B, orc):
+    # The adjoint workload at full size: N = 2048, 400 RK3 steps, the
+    # gradient of J = dx/2 sum (rho(T) - rho*)^2 with respect to the initial
+    # density (u0, p0 fixed) at 64 seeded cells ahead of the shock, each
+    # against the oracle's forward-mode derivative along that cell through
+    # the same recorded steps (replayed dt and speeds, decisions on real
+    # parts).  Bar: 1e-10 relative, with a floor of 1e-10 of the largest
+    # derivative for cells whose own derivative is tiny.
+    N, steps = 2048, 400
+    prob, U0, Utarget = _loss_setup(N)
+    dx = prob.dx[0]
+    rec = _recorder(B, prob)
+    tgt, _, _ = rec.forward(torch.from_numpy(Utarget.copy()).cuda(), steps, 0.5)
+    rho_star = tgt[0].clone()
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    UK, log, ckpt = rec.forward(Ud, steps, 0.5)
+    lamT = torch.zeros_like(UK)
+    lamT[0] = dx * (UK[0] - rho_star)
+    lam0 = rec.backward(lamT, log, ckpt).cpu().numpy()
+    dts, alphas = _log_host(B, log)
+    u0 = U0[1] / U0[0]
+    grad_rho = lam0[0] + u0 * lam0[1] + 0.5 * u0 * u0 * lam0[2]
+    rng = np.random.default_rng(3)
+    x = prob.centres(0)
+    cells = rng.choice(np.nonzero(x >= -4.0)[0], 64, replace=False)
+    V = np.zeros((len(cells),) + U0.shape)
+    for k, i in enumerate(cells):
+        V[k, 0, 0, 0, i] = 1.0
+        V[k, 1, 0, 0, i] = u0[0, 0, i]
+        V[k, 2, 0, 0, i] = 0.5 * u0[0, 0, i] ** 2
+    UT, _ = orc.run_jvp(prob, U0, np.zeros_like(U0), dts, alphas)
+    assert np.array_equal(UT, UK.cpu().numpy())   # the oracle replays the same trajectory
+    VT = orc.run_jvp_batch(prob, U0, V, dts, alphas)
+    lam = lamT.cpu().numpy()
+    fwd = np.einsum("kcabi,cabi->k", VT, lam)
+    ad = grad_rho[0, 0, cells]
+    err = np.abs(ad - fwd)
+    floor = 1e-10 * float(np.abs(fwd).max())
+    worst = float((err / np.maximum(np.abs(fwd), 1e-300)).max())
+    print(f"[adjoint] {steps}-step gradient at {len(cells)} cells vs forward mode: max "
+          f"|ad - fwd| {err.max():.2e}, max relative {worst:.2e}, largest |dJ| "
+          f"{np.abs(fwd).max():.2e}", flush=True)
+    assert np.all(err <= 1e-10 * np.abs(fwd) + floor)
+
+
 def test_gradient_finite_differences_with_digest(torch, B):
-    # d J / d rho0 (u0, p0 fixed) against central differences h = 1e-6 with
-    # replayed dt and speeds, at cells whose cutoff masks do not change.  Bar:
-    # 1e-6 relative where the gradient is at least 10% of its largest value,
-    # else 1e-7 of that value (the difference quotient's rounding floor grows
-    # as 1/h and sits near 2e-8 of it here)
-    N, steps, ncheck = 2048, 100, 16
+    # The adjoint workload at full size (N = 2048, 400 steps): d J / d rho0
+    # (u0, p0 fixed) against central differences h = 1e-6 with replayed dt
+    # and speeds, at 64 cells whose cutoff masks do not change anywhere in
+    # the trajectory (seeded cells ahead of the shock are drawn until 64 such
+    # cells are found).  Bar: 1e-6 relative where the gradient is at least
+    # 10% of its largest value, else 1e-7 of that value (the difference
+    # quotient's rounding floor grows as 1/h and sits near 2e-8 of it here).
+    N, steps, ncheck = 2048, 400, 64
     prob, U0, Utarget = _loss_setup(N)
     dx = prob.dx[0]
     rec = _recorder(B, prob)
@@ -197,15 +244,23 @@ def test_gradient_finite_differences_with_digest(torch, B):
         UT = rec.replay(torch.from_numpy(Uin).cuda(), log, digest=True)
         return 0.5 * dx * float(((UT[0] - rho_star) ** 2).sum()), rec.digest()
 
+    def J_free(Uin):
+        # the same steps with dt and the speeds recomputed from the perturbed
+        # states (the map the adjoint does not differentiate)
+        UT, _, _ = rec.forward(torch.from_numpy(Uin).cuda(), steps, 0.5)
+        return 0.5 * dx * float(((UT[0] - rho_star) ** 2).sum())
+
     Jb, db = J(U0)
     assert db == base_digest
     rng = np.random.default_rng(3)
     x = prob.centres(0)
-    cells = rng.choice(np.nonzero(x >= -4.0)[0], 64, replace=False)
+    order = rng.permutation(np.nonzero(x >= -4.0)[0])
     h = 1e-6
     gmax = float(np.abs(grad_rho).max())
     checked = skipped = 0
-    for i in cells:
+    worst = 0.0
+    gaps = []
+    for i in order:
         if checked == ncheck:
             break
         dU = np.zeros_like(U0)
@@ -219,10 +274,17 @@ def test_gradient_finite_differences_with_digest(torch, B):
             continue
         fd = (Jp - Jm) / (2 * h)
         ad = grad_rho[0, 0, i]
-        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 0.1 * gmax), (i, fd, ad, gmax)
+        bar = 1e-6 * max(abs(ad), 0.1 * gmax)
+        assert abs(fd - ad) <= bar, (i, fd, ad, gmax)
+        worst = max(worst, abs(fd - ad) / bar)
+        if len(gaps) < 4:
+            fd_free = (J_free(U0 + h * dU) - J_free(U0 - h * dU)) / (2 * h)
+            gaps.append(abs(fd_free - ad) / max(abs(ad), 0.1 * gmax))
         checked += 1
-    print(f"[adjoint] FD check: {checked} cells within 1e-6, {skipped} skipped (mask change)",
-          flush=True)
+    print(f"[adjoint] FD check, {steps} steps: {checked} cells within the bar (worst "
+          f"{worst:.2f} of it), {skipped} skipped (mask change); without replayed dt and "
+          f"speeds the difference quotient differs from the fixed-step gradient by "
+          f"{', '.join(f'{g:.1e}' for g in gaps)} (relative)", flush=True)
     assert checked == ncheck
 
 

@@ -46,16 +46,25 @@ def test_division_and_sqrt_correctly_rounded(torch):
     b = np.concatenate([b, rng.permutation(x2)])
     ad = torch.from_numpy(a).cuda()
     bd = torch.from_numpy(b).cuda()
-    q, q2, s, r = B.selftest_arith(ad, bd)
+    q, q2, s, r, qp, sp = B.selftest_arith(ad, bd, plain=True)
     torch.cuda.synchronize()
     q, q2, s, r = q.cpu().numpy(), q2.cpu().numpy(), s.cpu().numpy(), r.cpu().numpy()
+    qp, sp = qp.cpu().numpy(), sp.cpu().numpy()
     with np.errstate(all="ignore"):
         qe, se, re_ = a / b, np.sqrt(a), 1.0 / b
     bad_q = np.nonzero(q != qe)[0]
     bad_q2 = np.nonzero(q2 != qe)[0]
     bad_s = np.nonzero(s != se)[0]
+    # the compiler's plain a / b and sqrt on the same operands: how often
+    # they differ from IEEE-754 is what the correction layer is for
+    bad_qp = np.nonzero(qp != qe)[0]
+    bad_sp = np.nonzero(sp != se)[0]
     print(f"[arith] {len(a)} operands: div mismatches {len(bad_q)}, reciprocal-route div "
-          f"mismatches {len(bad_q2)}, sqrt mismatches {len(bad_s)}")
+          f"mismatches {len(bad_q2)}, sqrt mismatches {len(bad_s)}; uncorrected compiler "
+          f"a / b mismatches {len(bad_qp)}, sqrt mismatches {len(bad_sp)}", flush=True)
+    for i in list(bad_qp[:3]) + list(bad_sp[:3]):
+        print("   plain", repr(a[i]), repr(b[i]), repr(qp[i]), repr(qe[i]), repr(sp[i]),
+              repr(se[i]), flush=True)
     for i in list(bad_q[:5]) + list(bad_q2[:5]):
         print("   div", repr(a[i]), repr(b[i]), repr(q[i]), repr(q2[i]), repr(qe[i]))
     assert len(bad_q) == 0 and len(bad_q2) == 0 and len(bad_s) == 0

@@ -1,11 +1,15 @@
 """Host-side logic checked on the CPU: the multiply-and-shift constants that
 replace per-lane divisions by the line length (n + 1, n + 6) and the column
 count in the sweep kernels, the exactness of the fused power-of-two products,
+the map from a flipped decision to the cells the GPU parity tests leave out,
 and the kernel names under which bench.py looks up the sweeps' counters."""
 import os
 import subprocess
 
+import numpy as np
 import pytest
+
+from paper_2003_09145_amd import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_2003_09145_amd", "csrc")
@@ -112,3 +116,33 @@ def test_bench_sweep_names_resolve_in_counter_summary():
     for d in range(3):
         kname = f"k_sweep<3,{d},{bench.SWEEP_WAVES[d]},false>"
         assert len(bench.match_kernel(names, kname)) == 1, (kname, names)
+
+
+def test_cells_next_to_flips_mapping(orc):
+    # The GPU tests leave out the cells next to a face whose decision differs
+    # between two dumps.  Plant one differing byte at a known face of each
+    # axis of an oracle dump and check that exactly the face's two cells (one
+    # at a boundary face) are marked, located independently from the face's
+    # line and position.
+    from test_gpu_parity import cells_next_to_flips
+    prob = W.uniform_problem(3, [7, 5, 4], [0.0] * 3, [1.0] * 3, "periodic")
+    U = W.random_field(prob, seed=2)
+    _, dc = orc.rhs(prob, U, dump=True)
+    nx, ny, nz = prob.n
+    nc = prob.nc
+    off = 0
+    for d, (line, phi) in enumerate([(13, 3), (9, 0), (30, 4)]):
+        n = prob.n[d]
+        dg = dc.copy()
+        dg[off + (line * (n + 1) + phi) * 2 * nc + 2 * nc - 1] ^= 1
+        bad = cells_next_to_flips(prob, dg, dc)
+        # the sweep's line numbering: x lines by (z, y), y lines by (z, x),
+        # z lines by (y, x)
+        a, b = [(line % ny, line // ny), (line % nx, line // nx), (line % nx, line // nx)][d]
+        want = np.zeros((nz, ny, nx), dtype=bool)
+        for i in (phi - 1, phi):
+            if 0 <= i < n:
+                pos = {0: (b, a, i), 1: (b, i, a), 2: (i, b, a)}[d]
+                want[pos] = True
+        assert np.array_equal(bad, want), d
+        off += (prob.ncell // n) * (n + 1) * 2 * nc
