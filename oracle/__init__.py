@@ -112,7 +112,7 @@ def lib(literal: bool = False):
         L.or_advect_run.restype = ctypes.c_int64
         L.or_run_jvp_batch.argtypes = [P, dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp]
         L.or_run_jvp_batch.restype = ctypes.c_int
-        L.or_rhs_fluxabs.argtypes = [P, dp, dp, dp]
+        L.or_rhs_fluxabs.argtypes = [P, dp, dp, dp, dp]
         L.or_rhs_fluxabs.restype = ctypes.c_int
         L.or_literal.argtypes = []
         L.or_literal.restype = ctypes.c_int
@@ -249,15 +249,19 @@ def rhs(prob, U, alpha3=None, dump: bool = False, literal=False):
     return (out, dmp) if dump else out
 
 
-def rhs_flux_abs(prob, U, literal=False):
-    """(dUdt, S) with S[q] = sum over axes d and faces f of |F^_{f,q}| / dx_d,
-    the magnitude of the face-flux terms (for rounding bounds)."""
+def rhs_flux_abs(prob, U, literal=False, with_max=False):
+    """(dUdt, S[, M]): S[q] the sum over axes d and faces f of |F^_{f,q}| /
+    dx_d (the face-flux terms whose differences form the RHS), M[q] the max
+    over them of sum_s |R_qs f^_s| / dx_d (the terms the back-projection adds
+    into F^_q); magnitudes for rounding bounds."""
     p = params(prob)
     U = _f64(U)
     out = np.zeros_like(U)
     S = np.zeros(5)
-    lib(literal).or_rhs_fluxabs(ctypes.byref(p), _dp(U), _dp(out), _dp(S))
-    return out, S[:p.ndim + 2].copy()
+    M = np.zeros(5)
+    lib(literal).or_rhs_fluxabs(ctypes.byref(p), _dp(U), _dp(out), _dp(S), _dp(M))
+    nc = p.ndim + 2
+    return (out, S[:nc].copy(), M[:nc].copy()) if with_max else (out, S[:nc].copy())
 
 
 def rhs_cells(prob, U, alpha3, cells, dump: bool = False, literal=False):

@@ -515,7 +515,7 @@ void load_cell(const OrParams& P, const T* U, int d, const int base[3], int j,
  * the 2*nc decisions in the order (field s, sign +, sign -). */
 template <class T>
 void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
-               Decision* dec) {
+               Decision* dec, double* Fmag = nullptr) {
     int nd = P.ndim, nc = nd + 2;
     int perm[5];
     local_perm(nd, d, perm);
@@ -588,6 +588,11 @@ void face_flux(const OrParams& P, int d, T st[6][5], double alpha, T* Fhat,
         for (int s = 1; s < nc; ++s) acc = fmadd(Rm[q][s], fh[s], acc);
 #endif
         Fhat[perm[q]] = acc;
+        if (Fmag) {  /* sum_s |R_qs f^_s|: the terms the back-projection adds */
+            double m = 0.0;
+            for (int s = 0; s < nc; ++s) m += std::fabs(val(Rm[q][s]) * val(fh[s]));
+            Fmag[perm[q]] = m;
+        }
     }
 }
 
@@ -636,7 +641,8 @@ void lf_alpha(const OrParams& P, const double* U, double alpha[3], int* status) 
 /* ------------------------------------------------------------------------ */
 template <class T>
 void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
-              uint8_t* dump, double t, double* flux_abs = nullptr) {
+              uint8_t* dump, double t, double* flux_abs = nullptr,
+              double* flux_max = nullptr) {
     int nd = P.ndim, nc = nd + 2;
     int64_t N = ncells(P);
     for (int64_t i = 0; i < (int64_t)nc * N; ++i) out[i] = from_double<T>(0.0);
@@ -654,12 +660,14 @@ void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
             for (int j = -3; j < n + 3; ++j)
                 load_cell(P, U, d, base, j, &ext[(size_t)(j + 3) * 5], t);
             std::vector<T> fl((size_t)(n + 1) * 5);
+            std::vector<double> fmag(flux_max ? (size_t)(n + 1) * 5 : 0);
             for (int phi = 0; phi <= n; ++phi) {  /* face i+1/2, i = phi-1 */
                 T st[6][5];
                 for (int j = 0; j < 6; ++j)
                     for (int q = 0; q < nc; ++q) st[j][q] = ext[(size_t)(phi + j) * 5 + q];
                 Decision dec[10];
-                face_flux(P, d, st, alpha[d], &fl[(size_t)phi * 5], dump ? dec : nullptr);
+                face_flux(P, d, st, alpha[d], &fl[(size_t)phi * 5], dump ? dec : nullptr,
+                          flux_max ? &fmag[(size_t)phi * 5] : nullptr);
                 if (dump) {
                     uint8_t* o = dump + dump_off + ((size_t)l * (n + 1) + phi) * 2 * nc;
                     for (int k = 0; k < 2 * nc; ++k) o[k] = encode_decision(dec[k]);
@@ -675,14 +683,21 @@ void rhs_impl(const OrParams& P, const T* U, const double alpha[3], T* out,
                 }
             }
             if (flux_abs) {
-                /* sum over the line's faces of |F^| / dx (magnitudes for
-                 * rounding bounds; not part of the method) */
-                double loc[5] = {0, 0, 0, 0, 0};
+                /* sum over the line's faces of |F^| / dx and max of
+                 * sum_s |R_qs f^_s| / dx (magnitudes for rounding bounds; not
+                 * part of the method) */
+                double loc[5] = {0, 0, 0, 0, 0}, mx[5] = {0, 0, 0, 0, 0};
                 for (int phi = 0; phi <= n; ++phi)
-                    for (int q = 0; q < nc; ++q)
+                    for (int q = 0; q < nc; ++q) {
                         loc[q] += std::fabs(val(fl[(size_t)phi * 5 + q])) / dxd;
+                        double a = fmag[(size_t)phi * 5 + q] / dxd;
+                        if (a > mx[q]) mx[q] = a;
+                    }
 #pragma omp critical
-                for (int q = 0; q < nc; ++q) flux_abs[q] += loc[q];
+                for (int q = 0; q < nc; ++q) {
+                    flux_abs[q] += loc[q];
+                    if (mx[q] > flux_max[q]) flux_max[q] = mx[q];
+                }
             }
         }
         dump_off += L * (int64_t)(n + 1) * 2 * nc;
@@ -836,15 +851,17 @@ int or_rhs(const OrParams* P, const double* U, const double* alpha3,
     return st;
 }
 
-/* dUdt = L(U) as or_rhs, and flux_abs[q] = sum over axes d and faces f of
+/* dUdt = L(U) as or_rhs; flux_abs[q] = sum over axes d and faces f of
  * |F^_f,q| / dx_d (the magnitudes behind the rounding of the flux
- * differences, for conservation bounds). */
-int or_rhs_fluxabs(const OrParams* P, const double* U, double* dUdt, double* flux_abs) {
+ * differences) and flux_max[q] = max over them of sum_s |R_qs f^_s| / dx_d
+ * (those behind the rounding of the back-projection), for error bounds. */
+int or_rhs_fluxabs(const OrParams* P, const double* U, double* dUdt, double* flux_abs,
+                   double* flux_max) {
     double a[3];
     int st = 0;
     lf_alpha(*P, U, a, &st);
-    for (int q = 0; q < 5; ++q) flux_abs[q] = 0.0;
-    rhs_impl<double>(*P, U, a, dUdt, nullptr, P->time, flux_abs);
+    for (int q = 0; q < 5; ++q) flux_abs[q] = flux_max[q] = 0.0;
+    rhs_impl<double>(*P, U, a, dUdt, nullptr, P->time, flux_abs, flux_max);
     return st;
 }
 

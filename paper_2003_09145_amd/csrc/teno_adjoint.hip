@@ -36,8 +36,6 @@
 
 namespace teno {
 
-constexpr int kAdjChunk = 64;  // faces per pass-A chunk (one wave)
-
 // Derivative of the frozen-weight reconstruction sum_k omega_k q_k (eq
 // 2.4-2.6, 2.15) with respect to its m-th stencil value (a .. e = v_0 .. v_4)
 // for the weights w of one cutoff mask.
@@ -59,31 +57,12 @@ struct AdjArgs {
     const double* alpha;  // 3 device doubles
     double* P;            // chunk partials [chunk k][NC][cap][ncols]
     double* out;
-    int64_t ncell, line_step, stride, col_step, ftot, ncols;
-    int64_t kchunks;      // chunks per column
-    int32_t n, bc, accumulate, cap;
-    // multiply-and-shift division by n + 1, n + 6, ncols, n and the line count
-    // of a DIR-2 column (dividends < 2^31); div32: every cell, face and ext
-    // index is below 2^31
-    uint32_t m1, s1, m6, s6, mc, sc, mn, sn, mb, sb;
-    int32_t div32;
-    int32_t nb;  // lines of a DIR-2 column (ny)
+    AdjGeom G;            // geometry of the axis (teno_index.hpp)
+    int32_t accumulate;
     double dx;
     SchemeParams sch;
     DecisionConsts dk;
 };
-
-// Stencil cell jq - 3 of the extended line numbering (n + 6 cells per line,
-// three ghost cells at each end) starting from line be0: its line, its
-// interior source cell and whether the ghost image flips the normal momentum.
-__device__ __forceinline__ int64_t ext_source(const AdjArgs& A, int64_t colbase, int64_t be0,
-                                              int jq, bool* flip) {
-    const int np6 = A.n + 6;
-    const int bw = div_by(jq, A.m6, A.s6);
-    const int j = jq - bw * np6 - 3;
-    const int src = ghost_src(A.bc, A.n, j, flip);
-    return colbase + (be0 + bw) * A.line_step + (int64_t)src * A.stride;
-}
 
 template <int ND, int DIR, bool A5>
 __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
@@ -91,7 +70,8 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
     extern __shared__ double smem[];
-    const int cap = A.cap;
+    const AdjGeom& G = A.G;
+    const int cap = G.cap;
     double* omega = smem;       // 24: eq 2.15 weights per cutoff mask
     double* ctab = smem + 24;   // 40: cand_coef per (mask, stencil value)
     double* ext = smem + 64;    // NV x cap staged rows (forward quantities)
@@ -101,41 +81,24 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     if (lane < 24) omega[lane] = kOmega[lane / 3][lane % 3];
     if (lane < 40) ctab[lane] = cand_coef(&kOmega[lane / 5][0], lane % 5);
 
-    const int64_t chunk = xcd_logical_block(blockIdx.x, gridDim.x);
-    int64_t col = 0, k = chunk;
-    if (DIR != 0) {  // columns fastest, as in the forward sweep
-        k = div_by((int)chunk, A.mc, A.sc);  // chunk < kchunks ncols < 2^31
-        col = chunk - k * A.ncols;
-    }
-    const int n = A.n;
-    const int64_t np1 = n + 1, np6 = n + 6;
-    const int64_t colbase = col * A.col_step;
-    const int64_t F0 = k * kAdjChunk;
-    const int64_t F = F0 + lane;
-    const bool valid = F < A.ftot;
-    const int64_t Fc = valid ? F : F0;
-    const int64_t bl0 = A.div32 ? (int64_t)div_by((int)F0, A.m1, A.s1) : F0 / np1;
-    const int phi0 = (int)(F0 - bl0 * np1);
-    const int tq = phi0 + (int)(Fc - F0);
-    const int wraps = div_by(tq, A.m1, A.s1);
-    const int64_t bl = bl0 + wraps;             // line of this lane's face
-    const int phi = tq - wraps * (int)np1;      // face index in the line
-    const int64_t e_lo = F0 + 5 * bl0;
-    int64_t Flast = F0 + kAdjChunk - 1;
-    if (Flast > A.ftot - 1) Flast = A.ftot - 1;
-    const int count = (int)(Flast + 5 * (A.div32 ? (int64_t)div_by((int)Flast, A.m1, A.s1)
-                                                  : Flast / np1) + 6 - e_lo);
-    const int64_t be0 = A.div32 ? (int64_t)div_by((int)e_lo, A.m6, A.s6) : e_lo / np6;
-    const int je0 = (int)(e_lo - be0 * np6);
+    // columns fastest for y and z, as in the forward sweep
+    const AdjChunk C = adj_chunk(G, DIR, xcd_logical_block(blockIdx.x, gridDim.x));
+    const int n = G.n;
+    const int64_t k = C.k, col = C.col, colbase = C.colbase;
+    const bool valid = C.F0 + lane < G.ftot;
+    int64_t bl;  // line of this lane's face
+    int phi, o;  // face index in the line; staged offset of its cell i-2
+    adj_lane_face(G, C, valid ? lane : 0, &bl, &phi, &o);
+    const int count = C.count;
     const double alpha = A.alpha[DIR];
     const double gm1 = A.sch.gamma - 1.0;
 
     // ---- stage the chunk's cells exactly as the forward sweep does ---------
     // conserved state of staged cell idx as stored (ghost flip not applied)
     auto load_ext = [&](int idx, double* q, bool* flip) {
-        const int64_t cell = ext_source(A, colbase, be0, je0 + idx, flip);
+        const int64_t cell = adj_staged_cell(G, C, idx, flip);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = A.U[c * A.ncell + cell];
+        for (int c = 0; c < NC; ++c) q[c] = A.U[c * G.ncell + cell];
     };
     {
         // one cell ahead: the next cell's loads are in flight meanwhile
@@ -160,15 +123,14 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     __syncthreads();
 
     if (valid) {
-        const int o = (int)(Fc + 5 * bl - e_lo);  // ext offset of the face's cell i-2
         // cotangent of the face flux (local order)
-        const int64_t lbase = colbase + bl * A.line_step;
+        const int64_t lbase = colbase + bl * G.line_step;
         double mul[NC];
 #pragma unroll
         for (int qq = 0; qq < NC; ++qq) {
             const int64_t c = LO::nat(qq);
-            const double lr = (phi <= n - 1) ? A.lam[c * A.ncell + lbase + (int64_t)phi * A.stride] : 0.0;
-            const double ll = (phi >= 1) ? A.lam[c * A.ncell + lbase + (int64_t)(phi - 1) * A.stride] : 0.0;
+            const double lr = (phi <= n - 1) ? A.lam[c * G.ncell + lbase + (int64_t)phi * G.stride] : 0.0;
+            const double ll = (phi >= 1) ? A.lam[c * G.ncell + lbase + (int64_t)(phi - 1) * G.stride] : 0.0;
             mul[qq] = (lr - ll) / A.dx;
         }
         const FaceRoe<ND> R = face_roe<ND, DIR>(ext, cap, o, gm1);
@@ -419,8 +381,7 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         gq[NC - 1] += E_b;
         if (flip) gq[1 + DIR] = -gq[1 + DIR];  // ghost image: back to the source's frame
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            A.P[((k * NC + c) * cap + idx) * A.ncols + col] = gq[c];
+        for (int c = 0; c < NC; ++c) A.P[adj_p_index(G, NC, k, c, idx, col)] = gq[c];
     }
 }
 
@@ -428,82 +389,32 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
 template <int ND, int DIR>
 __global__ __launch_bounds__(256) void k_adj_gather(AdjArgs A) {
     constexpr int NC = ND + 2;
+    const AdjGeom& G = A.G;
     const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (cell >= A.ncell) return;
-    // (column, line, position) of the cell along DIR
-    int64_t col, b;
-    int i;
-    if (A.div32) {
-        if (DIR == 0) {
-            col = 0;
-            b = div_by((int)cell, A.mn, A.sn);
-            i = (int)(cell - b * A.n);
-        } else {
-            const int64_t rest = div_by((int)cell, A.mc, A.sc);  // (z, y) for DIR 1: y fastest
-            col = cell - rest * A.ncols;
-            const int64_t hi = div_by((int)rest, DIR == 1 ? A.mn : A.mb, DIR == 1 ? A.sn : A.sb);
-            const int64_t lo = rest - hi * (DIR == 1 ? A.n : A.nb);
-            if (DIR == 1) {
-                i = (int)lo;
-                b = hi;
-            } else {  // DIR 2: rest = z ny + y, lines ordered by y
-                b = lo;
-                i = (int)hi;
-            }
-        }
-    } else if (DIR == 0) {
-        col = 0;
-        b = cell / A.n;
-        i = (int)(cell - b * A.n);
-    } else {
-        col = cell % A.ncols;
-        const int64_t rest = cell / A.ncols;
-        if (DIR == 1) {
-            i = (int)(rest % A.n);
-            b = rest / A.n;
-        } else {
-            const int64_t ny = A.stride / A.ncols;
-            b = rest % ny;
-            i = (int)(rest / ny);
-        }
-    }
-    const int n = A.n;
+    if (cell >= G.ncell) return;
+    int64_t col, b;  // column and line of the cell along DIR
+    int i;           // its position on the line
+    adj_cell_place(G, DIR, cell, &col, &b, &i);
     // images of the cell on its line: itself and the ghost cells it supplies
     int img[7];
-    int nimg = 0;
-    img[nimg++] = i;
-    if (A.bc == TENO_BC_PERIODIC) {
-        if (i >= n - 3) img[nimg++] = i - n;
-        if (i <= 2) img[nimg++] = i + n;
-    } else if (A.bc == TENO_BC_TRANSMISSIVE) {
-        if (i == 0) { img[nimg++] = -1; img[nimg++] = -2; img[nimg++] = -3; }
-        if (i == n - 1) { img[nimg++] = n; img[nimg++] = n + 1; img[nimg++] = n + 2; }
-    } else {
-        if (i <= 2) img[nimg++] = -1 - i;
-        if (i >= n - 3) img[nimg++] = 2 * n - 1 - i;
-    }
+    const int nimg = adj_images(G.bc, G.n, i, img);
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    const int64_t np1 = n + 1;
     for (int t = 0; t < nimg; ++t) {
-        // extended cell e of line b is in the stencils of faces e-5 .. e
+        // staged cell e = image + 3 of line b is in the stencils of faces e-5 .. e
         const int e = img[t] + 3;
-        const int64_t E = b * (n + 6) + e;
-        const int64_t Fa = b * np1 + (e - 5 > 0 ? e - 5 : 0);
-        const int64_t Fz = b * np1 + (e < n ? e : n);
-        const int64_t ka = Fa / kAdjChunk, kz = Fz / kAdjChunk;
+        int64_t ka, kz;
+        adj_chunks_of(G, b, e, &ka, &kz);
         for (int64_t kk = ka; kk <= kz; ++kk) {
-            const int64_t F0 = kk * kAdjChunk;
-            const int64_t slot =
-                E - (F0 + 5 * (A.div32 ? (int64_t)div_by((int)F0, A.m1, A.s1) : F0 / np1));
+            const int slot = (int)adj_slot(G, b, e, kk);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += A.P[((kk * NC + c) * A.cap + slot) * A.ncols + col];
+            for (int c = 0; c < NC; ++c) acc[c] += A.P[adj_p_index(G, NC, kk, c, slot, col)];
         }
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double* o = A.out + c * A.ncell + cell;
+        double* o = A.out + c * G.ncell + cell;
         *o = A.accumulate ? *o + acc[c] : acc[c];
     }
 }
@@ -526,35 +437,11 @@ __global__ void k_adj_combo(int which, int64_t n, const double* dtp, const doubl
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-// Launch geometry of one axis: faces of a column, columns, and the chunk
-// partial buffer (chunks per column x NC x cap x columns doubles).
-struct AdjAxis {
-    int64_t ncols, col_step, line_step, stride, ftot, kchunks;
-    int cap;
-};
-
-static AdjAxis adj_axis(const teno_grid* g, int d) {
-    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
-    AdjAxis X;
-    int64_t lines;
-    if (d == 0) {
-        X.ncols = 1; X.col_step = 0; X.line_step = nx; X.stride = 1; lines = ny * nz;
-    } else if (d == 1) {
-        X.ncols = nx; X.col_step = 1; X.line_step = nx * ny; X.stride = nx; lines = nz;
-    } else {
-        X.ncols = nx; X.col_step = 1; X.line_step = nx; X.stride = nx * ny; lines = ny;
-    }
-    X.ftot = lines * (g->n[d] + 1);
-    X.kchunks = (X.ftot + kAdjChunk - 1) / kAdjChunk;
-    X.cap = ext_cap_for(g->n[d]);
-    return X;
-}
-
 static size_t adj_P_bytes(const teno_grid* g) {
     size_t mx = 0;
     for (int d = 0; d < g->ndim; ++d) {
-        const AdjAxis X = adj_axis(g, d);
-        const size_t b = (size_t)X.kchunks * (g->ndim + 2) * X.cap * X.ncols * sizeof(double);
+        const AdjGeom G = adj_geom(g->n, g->bc, d);
+        const size_t b = (size_t)adj_p_elems(G, g->ndim + 2) * sizeof(double);
         if (b > mx) mx = b;
     }
     return mx;
@@ -571,21 +458,20 @@ static size_t adj_ws_bytes(const teno_grid* g) {
 template <int ND, int DIR>
 static hipError_t launch_adj(AdjArgs A, hipStream_t st) {
     constexpr int NV = 2 * (ND + 2) + ND + 2;
-    const int64_t nblk = A.kchunks * A.ncols;
-    const size_t lds = (size_t)(64 + 2 * NV * A.cap) * sizeof(double);
+    const int64_t nblk = A.G.kchunks * A.G.ncols;
+    const size_t lds = (size_t)(64 + 2 * NV * A.G.cap) * sizeof(double);
     if (A.sch.scheme == TENO_SCHEME_TENO5A)
         hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true>), dim3((unsigned)nblk), dim3(64), lds, st, A);
     else
         hipLaunchKernelGGL((k_adj_chunk<ND, DIR, false>), dim3((unsigned)nblk), dim3(64), lds, st, A);
-    hipLaunchKernelGGL((k_adj_gather<ND, DIR>), dim3((unsigned)((A.ncell + 255) / 256)), dim3(256), 0,
-                       st, A);
+    hipLaunchKernelGGL((k_adj_gather<ND, DIR>), dim3((unsigned)((A.G.ncell + 255) / 256)), dim3(256),
+                       0, st, A);
     return hipGetLastError();
 }
 
 static hipError_t rhs_adjoint_impl(const teno_grid* g, const double* U, const double* alpha,
                                    const double* lam, double* out, double* P, hipStream_t st) {
     for (int d = 0; d < g->ndim; ++d) {
-        const AdjAxis X = adj_axis(g, d);
         AdjArgs A;
         memset(&A, 0, sizeof(A));
         A.U = U;
@@ -593,31 +479,12 @@ static hipError_t rhs_adjoint_impl(const teno_grid* g, const double* U, const do
         A.alpha = alpha;
         A.P = P;
         A.out = out;
-        A.ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
-        A.n = g->n[d];
-        A.bc = g->bc[d];
+        A.G = adj_geom(g->n, g->bc, d);
         A.dx = g->dx[d];
         A.accumulate = d > 0;
-        A.cap = X.cap;
         A.sch = scheme_of(g);
         A.dk = decision_consts(g, false);
-        A.ncols = X.ncols;
-        A.col_step = X.col_step;
-        A.line_step = X.line_step;
-        A.stride = X.stride;
-        A.ftot = X.ftot;
-        A.kchunks = X.kchunks;
-        if (A.kchunks * A.ncols > (int64_t(1) << 31) - 64) return hipErrorInvalidValue;
-        const int64_t nb = (d == 2) ? A.stride / A.ncols : 1;  // lines of a DIR-2 column
-        const DivMagic d1 = div_magic((uint32_t)(A.n + 1)), d6 = div_magic((uint32_t)(A.n + 6)),
-                       dc = div_magic((uint32_t)A.ncols), dn = div_magic((uint32_t)A.n),
-                       db = div_magic((uint32_t)nb);
-        A.m1 = d1.m; A.s1 = d1.sh; A.m6 = d6.m; A.s6 = d6.sh; A.mc = dc.m; A.sc = dc.sh;
-        A.mn = dn.m; A.sn = dn.sh; A.mb = db.m; A.sb = db.sh;
-        A.nb = (int32_t)nb;
-        // largest index: a cell, or an ext index ftot + 5 lines (+ a chunk's tail)
-        const int64_t lines = A.ftot / (A.n + 1);
-        A.div32 = (A.ncell < (int64_t(1) << 31) && A.ftot + 6 * lines + 128 < (int64_t(1) << 31)) ? 1 : 0;
+        if (A.G.kchunks * A.G.ncols > (int64_t(1) << 31) - 64) return hipErrorInvalidValue;
         hipError_t e = hipErrorInvalidValue;
         switch (g->ndim * 4 + d) {
             case 4: e = launch_adj<1, 0>(A, st); break;

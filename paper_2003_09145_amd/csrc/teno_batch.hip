@@ -33,8 +33,6 @@
 
 namespace teno {
 
-constexpr int kBatchCells = 63;
-
 struct BatchArgs {
     const double* Uin;          // stage input state [3][total]
     const double* Un;           // u^n
@@ -53,17 +51,6 @@ struct BatchArgs {
     SchemeParams sch;
     DecisionConsts dk;
 };
-
-// Largest tube b' >= b whose first face (off[b'] + b') is <= F.
-__device__ __forceinline__ int tube_of_face(const int64_t* off, int nb, int b, int64_t F) {
-    while (b + 1 < nb && off[b + 1] + (b + 1) <= F) ++b;
-    return b;
-}
-// Largest tube b' >= b whose first ghost cell (off[b'] + 6 b') is <= e.
-__device__ __forceinline__ int tube_of_ext(const int64_t* off, int nb, int b, int64_t e) {
-    while (b + 1 < nb && off[b + 1] + 6 * (int64_t)(b + 1) <= e) ++b;
-    return b;
-}
 
 // Per-cell LF speed |u| + c of a 1D state (the operation order of the grid
 // path's reduction) and its physicality.
@@ -106,8 +93,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     extern __shared__ double smem[];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    static_assert(NV == 9 && NC == 3, "batch_wave_lds assumes the 1D row count");
     const int cap = A.ext_cap;
-    const int per_wave = (cap * NV > 64 * NC) ? cap * NV : 64 * NC;
+    const int per_wave = batch_wave_lds(cap);
     double* omega = smem;
     double* ext = smem + 24 + (size_t)wave * per_wave;
     double* fhs = ext;  // reused after the wave's stencil reads (in-order LDS)
@@ -132,27 +120,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t chunk = g * W + wave;
         const bool wave_ok = chunk < A.nchunks;
-        const int t0 = wave_ok ? A.chunk_tube[chunk] : 0;
-        const int64_t F0 = chunk * kBatchCells;
-        const int64_t F = F0 + lane;
+        const BatchChunk C =
+            batch_chunk(A.off, nb, A.ftot, wave_ok ? chunk : 0, wave_ok ? A.chunk_tube[chunk] : 0);
+        const int count = wave_ok ? C.count : 0;
+        const int64_t F = C.F0 + lane;
         const bool valid = wave_ok && F < A.ftot;
-        const int b = valid ? tube_of_face(A.off, nb, t0, F) : t0;
-        const int64_t phi = F - (A.off[b] + b);
-        const int64_t e_lo = F0 + 5 * (int64_t)t0;
-        int64_t Flast = F0 + 63;
-        if (Flast > A.ftot - 1) Flast = A.ftot - 1;
-        const int b_last = wave_ok ? tube_of_face(A.off, nb, t0, Flast) : t0;
-        const int count = wave_ok ? (int)(Flast + 5 * (int64_t)b_last + 6 - e_lo) : 0;
+        int b = C.t0, o = 0;
+        int64_t phi = 0;
+        if (valid) batch_face(A.off, nb, C, F, &b, &phi, &o);
         __syncthreads();  // the previous chunk group's LDS reads are done
 
         for (int idx = lane; idx < count; idx += 64) {
-            const int64_t e = e_lo + idx;
-            const int bb = tube_of_ext(A.off, nb, t0, e);
-            const int64_t base = A.off[bb];
-            const int n = (int)(A.off[bb + 1] - base);
-            const int j = (int)(e - (base + 6 * (int64_t)bb)) - 3;
+            int bb;
             bool flip;
-            const int src = ghost_src(A.bc, n, j, &flip);
+            const int src = batch_staged_src(A.off, nb, A.bc, C, idx, &bb, &flip);
+            const int64_t base = A.off[bb];
             double q[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) q[c] = A.Uin[c * A.total + base + src];
@@ -162,7 +144,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
         __syncthreads();
 
         if (valid) {
-            const int o = (int)(F + 5 * (int64_t)b - e_lo);
             double Fh[NC];
             face_flux<ND, DIR, A5>(ext, cap, o, gm1, A.sch, A.dk, omega, nullptr, Fh);
 #pragma unroll
@@ -304,9 +285,7 @@ struct teno_batch_plan {
 namespace {
 
 size_t lds_bytes(const teno_batch_plan* P, int W) {
-    constexpr int NC = 3, NV = 9;
-    const int per_wave = (P->ext_cap * NV > 64 * NC) ? P->ext_cap * NV : 64 * NC;
-    return (size_t)(24 + W * per_wave) * sizeof(double);
+    return (size_t)(24 + W * batch_wave_lds(P->ext_cap)) * sizeof(double);
 }
 
 int64_t grid_for(const teno_batch_plan* P, int W, int bpc) {
@@ -445,12 +424,7 @@ int teno_batch_plan_create(const teno_grid* g, int64_t nbatch, const int64_t* le
     P->cfl = cfl;
     P->t_end = t_end;
     std::vector<int32_t> ct((size_t)P->nchunks);
-    int64_t b = 0;
-    for (int64_t k = 0; k < P->nchunks; ++k) {
-        const int64_t F0 = k * kBatchCells;
-        while (b + 1 < nbatch && off[(size_t)b + 1] + (b + 1) <= F0) ++b;
-        ct[(size_t)k] = (int32_t)b;
-    }
+    batch_chunk_tubes(off.data(), nbatch, P->nchunks, ct.data());
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "teno_index.hpp"
+
 namespace teno {
 
 // Scheme parameters as the kernels see them (copied from teno_grid).
@@ -436,30 +438,6 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
     const double f2 = __builtin_fma(-kC1_6, e, __builtin_fma(kC1_3, c, kC5_6 * d));
     const double* w = omega_lds + 3 * mask;
     return __builtin_fma(w[2], f2, __builtin_fma(w[0], f0, w[1] * f1));
-}
-
-// Ghost-cell source along a swept axis: periodic wrap, zero-gradient copy or
-// reflecting mirror (normal momentum negated), three cells per side.
-__device__ __forceinline__ int ghost_src(int bc, int n, int j, bool* flip) {
-    *flip = false;
-    if (j >= 0 && j < n) return j;
-    if (bc == 0) return j < 0 ? j + n : j - n;  // |j| <= 3 <= n
-    if (bc == 1) return j < 0 ? 0 : n - 1;
-    *flip = true;
-    return j < 0 ? -1 - j : 2 * n - 1 - j;
-}
-
-// floor(x / d) for 0 <= x < 2^31 from the host's DivMagic constants of d.
-__device__ __forceinline__ int div_by(int x, uint32_t m, uint32_t sh) {
-    return (int)(((uint64_t)(uint32_t)x * m) >> sh);
-}
-
-// Map the hardware block index to a logical index such that blocks that run
-// on the same XCD (hardware assigns block b to XCD b % 8) get consecutive
-// logical indices, so neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t G) {
-    const int64_t q = G / 8, r = G % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
 }
 
 // Local component order of a sweep along DIR: rho, normal momentum, the

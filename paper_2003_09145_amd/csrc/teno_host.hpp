@@ -63,7 +63,6 @@ inline SchemeParams scheme_of(const teno_grid* g) {
     return s;
 }
 
-inline int ext_cap_for(int n) { return 69 + 5 * (63 / (n + 1) + 1); }
 
 // The literal LAD ladder index of eq 3.1-3.2 evaluated on the host (IEEE
 // binary64, round to nearest): m(x) = B_l + floor(theta (B_u - B_l)),

@@ -146,3 +146,62 @@ def test_cells_next_to_flips_mapping(orc):
                 want[pos] = True
         assert np.array_equal(bad, want), d
         off += (prob.ncell // n) * (n + 1) * 2 * nc
+
+
+# --------------------------------------------------------------------------
+# Index maps of the batched-tube kernel and the adjoint's chunked passes
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def index_check(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("idx") / "index_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, "-o", exe,
+                    os.path.join(HERE, "harness", "index_check.cpp")], check=True)
+    return exe
+
+
+def _small_batch_lengths(seed, count):
+    # the tube lengths of the batched GPU tests (3 .. 200 cells, several tubes
+    # sharing one 64-face chunk)
+    rng = np.random.default_rng(seed)
+    return np.concatenate([[3, 4, 5, 6, 7, 64, 63, 65], rng.integers(3, 200, count - 8)])
+
+
+@pytest.mark.parametrize("name", ["small_7_37", "small_3_30", "small_9_10", "full_4096",
+                                  "all_length_3", "lengths_3_to_5", "one_long_tube"])
+def test_batch_index_maps(index_check, tmp_path, name):
+    # Every chunk and lane of the batched stage kernel, through the same
+    # index functions the kernel calls: staged sources inside their tubes,
+    # stencils inside the staged window (<= the LDS rows), each cell updated
+    # by exactly one lane and each tube's dt written by exactly one lane.
+    lengths = {
+        "small_7_37": lambda: _small_batch_lengths(7, 37),
+        "small_3_30": lambda: _small_batch_lengths(3, 30),
+        "small_9_10": lambda: _small_batch_lengths(9, 10),
+        "full_4096": lambda: W.batched_tubes().lengths,
+        "all_length_3": lambda: np.full(700, 3),
+        "lengths_3_to_5": lambda: np.random.default_rng(1).integers(3, 6, 3000),
+        "one_long_tube": lambda: np.array([5, 100000, 3, 4]),
+    }[name]()
+    f = tmp_path / "lengths.bin"
+    np.asarray(lengths, dtype=np.int64).tofile(f)
+    for bc in (1, 0, 2):
+        r = subprocess.run([index_check, "batch", str(bc), str(f)], capture_output=True, text=True)
+        print(r.stdout.strip())
+        assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("shape,nd,bc", [
+    ((256, 256, 256), 3, (0, 0, 0)), ((128, 128, 128), 3, (0, 1, 2)),
+    ((20, 1, 1), 1, (0, 0, 0)), ((17, 1, 1), 1, (2, 0, 0)), ((2048, 1, 1), 1, (1, 0, 0)),
+    ((8, 7, 1), 2, (2, 0, 0)), ((63, 66, 1), 2, (2, 0, 0)), ((130, 67, 1), 2, (1, 0, 0)),
+    ((5, 5, 4), 3, (1, 0, 2)), ((70, 66, 9), 3, (0, 2, 1)), ((9, 5, 131), 3, (2, 1, 0)),
+    ((3, 3, 3), 3, (2, 2, 2)), ((64, 65, 70), 3, (0, 2, 1))])
+def test_adjoint_index_maps(index_check, shape, nd, bc):
+    # Every chunk of the adjoint's pass A and every cell of its gather, through
+    # the kernels' index functions: staged cells, partial-buffer writes within
+    # the workspace's partial area, lane faces inside the staged window, and
+    # every partial the gather reads written by its chunk.
+    r = subprocess.run([index_check, "adj", *map(str, shape), str(nd), *map(str, bc)],
+                       capture_output=True, text=True)
+    print(r.stdout.strip())
+    assert r.returncode == 0, r.stderr
