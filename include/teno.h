@@ -190,6 +190,21 @@ int teno_rhs(const teno_grid* g, const double* U_dev, double* dUdt_dev,
              const double* alpha_in_dev, double* alpha_out_dev,
              int32_t* status_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): L(U)
+ * exactly as teno_rhs (the same kernels, bit-identical results), with no
+ * workspace argument.  The LF-speed partials and the speeds in use live in a
+ * fixed 72 KiB device array of the library, one copy per GPU, looked up on
+ * the first call on each device and held until the process ends; the call
+ * allocates nothing.  Its size does not depend on the grid, so every grid
+ * teno_rhs accepts is accepted (invalid arguments: TENO_ERR_ARG, a failed
+ * address lookup or launch: TENO_ERR_DEVICE).  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (several streams or
+ * threads) race and must be ordered by the caller. */
+int teno_rhs_noalloc(const teno_grid* g, const double* U_dev, double* dUdt_dev,
+                     const double* alpha_in_dev, double* alpha_out_dev,
+                     int32_t* status_dev, void* stream);
+
 /* As teno_rhs, and also writes the cutoff decisions of every scalar
  * reconstruction: per axis d (x, y, z), per line, per face phi = i + 1 in
  * [0, n_d], 2*ncomp bytes (characteristic field s, sign + then -), each byte

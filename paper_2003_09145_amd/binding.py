@@ -89,7 +89,7 @@ assert CTRL_BYTES == 152
 
 # Every symbol declared in include/teno.h (checked by the ABI tests).
 SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_ctrl_replay", "teno_ctrl_digest",
-           "teno_rhs", "teno_rhs_debug", "teno_sweep",
+           "teno_rhs", "teno_rhs_noalloc", "teno_rhs_debug", "teno_sweep",
            "teno_selftest_arith", "teno_step", "teno_step_timed",
            "teno_adjoint_workspace_bytes", "teno_rhs_adjoint", "teno_step_adjoint",
            "teno_advect_workspace_bytes", "teno_advect_rhs", "teno_advect_step",
@@ -124,6 +124,8 @@ def lib():
         L.teno_ctrl_digest.restype = ctypes.c_int
         L.teno_rhs.argtypes = [G, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_rhs.restype = ctypes.c_int
+        L.teno_rhs_noalloc.argtypes = [G, vp, vp, vp, vp, vp, vp]
+        L.teno_rhs_noalloc.restype = ctypes.c_int
         L.teno_rhs_debug.argtypes = [G, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.teno_rhs_debug.restype = ctypes.c_int
         L.teno_sweep.argtypes = [G, ctypes.c_int32, vp, vp, vp, vp, vp]
@@ -284,6 +286,12 @@ def teno_rhs(g, U, dUdt, ws, alpha_in=None, alpha_out=None, status=None, stream=
     _check(lib().teno_rhs(ctypes.byref(g), _ptr(U), _ptr(dUdt), _ptr(alpha_in), _ptr(alpha_out),
                           _ptr(status), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
            "teno_rhs")
+
+
+def teno_rhs_noalloc(g, U, dUdt, alpha_in=None, alpha_out=None, status=None, stream=None):
+    _check(lib().teno_rhs_noalloc(ctypes.byref(g), _ptr(U), _ptr(dUdt), _ptr(alpha_in),
+                                  _ptr(alpha_out), _ptr(status), _stream(stream)),
+           "teno_rhs_noalloc")
 
 
 def teno_rhs_debug(g, U, dUdt, decisions, ws, alpha_in=None, alpha_out=None, status=None,

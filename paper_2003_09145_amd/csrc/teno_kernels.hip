@@ -17,6 +17,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/teno.h"
 #include "teno_device.hpp"
 #include "teno_face.hpp"
@@ -746,14 +748,10 @@ static hipError_t launch_alpha(const teno_grid* g, const double* U, double* part
     return hipGetLastError();
 }
 
-static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
-                      double* alpha_out, int32_t* status, uint8_t* dump, void* ws,
-                      size_t ws_bytes, void* stream) {
-    if (validate(g) != TENO_OK || U == nullptr || dUdt == nullptr || ws == nullptr ||
-        ws_bytes < workspace_bytes_impl(g))
-        return TENO_ERR_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    Scratch* S = scratch_of(g, ws);
+// L(U) with the LF-speed partials and the speeds in use in the scratch area S.
+static int rhs_with_scratch(const teno_grid* g, const double* U, double* dUdt,
+                            const double* alpha_in, double* alpha_out, int32_t* status,
+                            uint8_t* dump, Scratch* S, hipStream_t st) {
     if (alpha_in == nullptr) {
         if (launch_alpha(g, U, S->part, st) != hipSuccess) return TENO_ERR_DEVICE;
     }
@@ -773,6 +771,45 @@ static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const d
         if (launch_sweep(g, d, A, st) != hipSuccess) return TENO_ERR_DEVICE;
         dump_off += ncell_of(g) / g->n[d] * (int64_t)(g->n[d] + 1) * 2 * (g->ndim + 2);
     }
+    return TENO_OK;
+}
+
+static int rhs_common(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
+                      double* alpha_out, int32_t* status, uint8_t* dump, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (validate(g) != TENO_OK || U == nullptr || dUdt == nullptr || ws == nullptr ||
+        ws_bytes < workspace_bytes_impl(g))
+        return TENO_ERR_ARG;
+    return rhs_with_scratch(g, U, dUdt, alpha_in, alpha_out, status, dump, scratch_of(g, ws),
+                            (hipStream_t)stream);
+}
+
+// Scratch of the allocation-free RHS (teno_rhs_noalloc): a fixed device array
+// of the library, one copy per GPU, held until the process ends.  Its size
+// does not depend on the grid: the LF-speed reduction writes at most
+// kAlphaBlocks partials, whatever the number of cells.
+constexpr size_t kNoAllocScratchBytes = 72 * 1024;
+static_assert(sizeof(Scratch) <= kNoAllocScratchBytes, "the RHS scratch must fit the array");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on the current GPU.  In host code the array's
+// name is only a host-side stand-in, so the address is looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_dev[kMaxDevices];
+
+static int scratch_address(Scratch** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TENO_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_dev[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return TENO_ERR_DEVICE;
+        g_scratch_dev[dev] = p;
+    }
+    *out = (Scratch*)g_scratch_dev[dev];
     return TENO_OK;
 }
 
@@ -834,6 +871,19 @@ int teno_ctrl_digest(teno_ctrl* ctrl, int32_t enable, void* stream) {
 int teno_rhs(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
              double* alpha_out, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
     return rhs_common(g, U, dUdt, alpha_in, alpha_out, status, nullptr, ws, ws_bytes, stream);
+}
+
+int teno_rhs_noalloc(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
+                     double* alpha_out, int32_t* status, void* stream) {
+    if (validate(g) != TENO_OK || U == nullptr || dUdt == nullptr) return TENO_ERR_ARG;
+    Scratch* S = nullptr;
+    const int rc = scratch_address(&S);
+    if (rc != TENO_OK) return rc;
+    // nothing in the scratch needs to start at zero: the reduction reads only
+    // the partials this call's k_alpha writes, and k_copy_alpha overwrites
+    // the speeds in use
+    return rhs_with_scratch(g, U, dUdt, alpha_in, alpha_out, status, nullptr, S,
+                            (hipStream_t)stream);
 }
 
 int teno_rhs_debug(const teno_grid* g, const double* U, double* dUdt, const double* alpha_in,
