@@ -13,7 +13,10 @@ update (an RK3 step = 3 cell-updates per cell).
 Beside the headline the same JSON line carries
   roofline      the dominant kernel (the slowest sweep) timed with HIP events
                 around its launches inside the timed region;
-  cpu_baseline  the FP64 oracle timed on the host cores on one RK3 step;
+  cpu_baseline  the FP64 oracle timed on the host cores on one RK3 step of
+                the same input, and in the same run the GPU's first step
+                and one RHS (with every cutoff decision) compared with the
+                oracle's over the whole 256^3 field;
   schemes       2D four-quadrant Riemann problem at 2048^2 (eq 4.14 states),
                 TENO5-LAD against fixed-cutoff TENO5, TENO5-A (eq 2.16-2.18)
                 and the linear upwind scheme, next to the per-step times of
@@ -57,6 +60,7 @@ SWEEP_SOURCES = ["paper_2003_09145_amd/csrc/teno_kernels.hip",
                  "paper_2003_09145_amd/csrc/teno_face.hpp",
                  "paper_2003_09145_amd/csrc/teno_device.hpp",
                  "paper_2003_09145_amd/csrc/teno_host.hpp",
+                 "paper_2003_09145_amd/csrc/teno_index.hpp",
                  "paper_2003_09145_amd/csrc/teno_divmagic.hpp", "include/teno.h"]
 COPY_BYTES = 1 << 30
 
@@ -127,24 +131,37 @@ def match_kernel(names, kernel: str):
     return [k for k in names if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
 
 
-def load_traffic(kernel: str):
-    """Counter-measured HBM bytes per launch of `kernel` from the committed
-    summary, or None when the sweep sources changed since it was taken."""
+def _load_counter_rows(prefix: str, kernel: str):
+    """The key=value fields of the committed counter summary's `prefix` line
+    for `kernel`, or None when the sweep sources changed since it was taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     sha, vals = None, {}
     for line in open(TRAFFIC_FILE):
         if line.startswith("source_sha256:"):
             sha = line.split(":", 1)[1].strip()
-        elif line.startswith("kernel "):
-            name, rest = line[len("kernel "):].split(":", 1)
+        elif line.startswith(prefix + " "):
+            name, rest = line[len(prefix) + 1:].split(":", 1)
             kv = dict(x.strip().split("=") for x in rest.split(","))
             vals[name.strip()] = kv
     names = match_kernel(vals, kernel)
     if sha != sources_sha() or len(names) != 1:
         return None
-    kv = vals[names[0]]
-    return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return vals[names[0]]
+
+
+def load_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch of `kernel` from the committed
+    summary, or None when the sweep sources changed since it was taken."""
+    kv = _load_counter_rows("kernel", kernel)
+    return None if kv is None else float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+
+
+def load_executed_flop(kernel: str):
+    """Executed FP64 flop per launch of `kernel` (SQ_INSTS_VALU_{ADD,MUL,
+    TRANS}_F64 + 2 x FMA, x 64 lanes) from the committed summary, or None."""
+    kv = _load_counter_rows("valu", kernel)
+    return None if kv is None else float(kv["executed_f64_flop"])
 
 
 # --------------------------------------------------------------------------
@@ -199,6 +216,7 @@ def headline(args, B, W, torch):
     # the plain (digest-free) instantiation; waves per block by axis at 256^3
     kname = f"k_sweep<3,{dom},{SWEEP_WAVES[dom]},false>"
     traffic = load_traffic(kname)
+    executed = load_executed_flop(kname)
     alg_bytes = sweep_bytes(3, n3, dom, fused_rk=fused)
     roofline = {
         "bound": "alu",
@@ -215,6 +233,11 @@ def headline(args, B, W, torch):
         "hbm_algorithmic_frac": round(alg_bytes / (per_axis[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "hbm_counter_GBs": (None if traffic is None else
                             round(traffic / (per_axis[dom] * 1e-3) / 1e9, 1)),
+        # executed FP64 operations from the committed counters (rocprofv3
+        # SQ_INSTS_VALU_*_F64 of the same kernel) over the same launch time
+        "fp64_counter_flop_per_launch": executed,
+        "fp64_counter_frac": (None if executed is None else
+                              round(executed / (per_axis[dom] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)),
         "sweep_ms_xyz": [round(x, 4) for x in per_axis],
     }
     step_s = ms * 1e-3 / args.steps
@@ -621,20 +644,97 @@ def adjoint_leg(args, B, W, torch):
 
 
 # --------------------------------------------------------------------------
+# Measured HBM bandwidth: a plain device copy
+# --------------------------------------------------------------------------
+def hbm_copy_bandwidth(torch, nbytes=2 << 30, reps=10):
+    """GB/s of a plain device-to-device copy of nbytes (read + write counted),
+    HIP events over `reps` copies; the arrays far exceed the 256 MB
+    memory-side cache."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+# --------------------------------------------------------------------------
 # The oracle on the host cores
 # --------------------------------------------------------------------------
-def cpu_baseline(prob, U):
+def cpu_baseline(prob, U, B=None, torch=None):
+    """The oracle timed on one RK3 step of the headline input.  With the
+    binding given, the same run also checks the GPU against the oracle on
+    that input, element by element over the whole field: the first RK3 step
+    (both from U) and one RHS evaluation with every cutoff decision, against
+    the fused-order oracle and the FMA-free one."""
     import numpy as np
     import oracle
     U0 = np.ascontiguousarray(U)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.time()
-    oracle.step(prob, U0, 0.5, 0.0, float("inf"))
+    Uc, _, dtc, _, stc = oracle.step(prob, U0, 0.5, 0.0, float("inf"))
     el = time.time() - t0
-    return {"value": 3.0 * prob.ncell / el, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 RHS evaluations + stage updates) of the same "
-                      f"{prob.n[0]}^3 input, {el:.1f} s wall on {threads} OpenMP threads"}
+    out = {"value": 3.0 * prob.ncell / el, "unit": "cell-updates/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"one SSP-RK3 step (3 RHS evaluations + stage updates) of the same "
+                     f"{prob.n[0]}^3 input, {el:.1f} s wall on {threads} OpenMP threads"}
+    if B is None:
+        return out
+    nc = prob.nc
+
+    def rel(a, c):
+        scale = np.abs(c).reshape(nc, -1).max(axis=1)
+        scale = np.where(scale > 0, scale, 1.0)
+        return float((np.abs(a - c).reshape(nc, -1).max(axis=1) / scale).max())
+
+    S = B.Solver(prob)
+    Ud = torch.from_numpy(U0).cuda()
+    S.init(0.0, float("inf"), 0.5)
+    S.step(Ud)
+    torch.cuda.synchronize()
+    Ug = Ud.cpu().numpy()
+    par = {"step_max_rel": rel(Ug, Uc), "step_bitwise": bool(np.array_equal(Ug, Uc)),
+           "step_dt_equal": S.read_ctrl().dt == dtc}
+    del Ug, Uc
+    Ud.copy_(torch.from_numpy(U0))
+    R, dec = S.rhs(Ud, decisions=True)
+    torch.cuda.synchronize()
+    Rg, dg = R.cpu().numpy(), dec.cpu().numpy()
+    del R, dec, Ud, S
+    torch.cuda.empty_cache()
+    t1 = time.time()
+    Rc, dc = oracle.rhs(prob, U0, dump=True)
+    par.update({"rhs_flips": int(np.count_nonzero(dg != dc)), "rhs_max_rel": rel(Rg, Rc),
+                "rhs_bitwise": bool(np.array_equal(Rg, Rc))})
+    del Rc, dc
+    Rl, dl = oracle.rhs(prob, U0, dump=True, literal=True)
+    # against the FMA-free oracle the error is measured per component relative
+    # to the larger of the component's largest RHS and its largest
+    # back-projection term sum_s |R_cs f^_s| / dx: the mass RHS of this nearly
+    # solenoidal field is a small residual of much larger cancelling terms
+    _, _, fmax = oracle.rhs_flux_abs(prob, U0, literal=True, with_max=True)
+    scale = np.maximum(np.abs(Rl).reshape(nc, -1).max(axis=1), fmax)
+    par.update({"literal_rhs_flips": int(np.count_nonzero(dg != dl)),
+                "literal_rhs_max_rel": float((np.abs(Rg - Rl).reshape(nc, -1).max(axis=1) /
+                                              scale).max()),
+                "literal_rhs_max_rel_own_norm": rel(Rg, Rl)})
+    par["cells_compared"] = prob.ncell
+    par["oracle_check_wall_s"] = round(time.time() - t1, 2)
+    out["parity"] = par
+    print(f"[bench] 256^3 parity: step bitwise {par['step_bitwise']}, rhs flips {par['rhs_flips']} "
+          f"bitwise {par['rhs_bitwise']}; literal oracle flips {par['literal_rhs_flips']} "
+          f"max rel {par['literal_rhs_max_rel']:.2e}", file=sys.stderr, flush=True)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -924,6 +1024,11 @@ def main():
                                          "rhs_adjoint_over_rhs": a3 / r3}}), flush=True)
         return
     prob, U, value, ms, roofline, whole = headline(args, B, W, torch)
+    copy_gbs = hbm_copy_bandwidth(torch)
+    roofline["hbm_copy_measured_GBs"] = round(copy_gbs, 1)
+    roofline["hbm_algorithmic_frac_of_measured"] = round(
+        roofline["hbm_algorithmic_GBs"] / copy_gbs, 4)
+    print(f"[bench] plain device copy: {copy_gbs:.1f} GB/s", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": value,
@@ -953,7 +1058,7 @@ def main():
                                      "was reported during their parity test"}
         out["adjoint"] = adjoint_leg(args, B, W, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, U)
+        out["cpu_baseline"] = cpu_baseline(prob, U, B, torch)
     print(json.dumps(out), flush=True)
 
 
