@@ -23,6 +23,7 @@ struct SchemeParams {
     int32_t scheme;  // 0 LAD, 1 fixed C_T, 2 linear (all stencils kept), 3 TENO5-A
     int32_t Bl, Bu;
     int32_t kA_nan;  // TENO5-A: exponent taken by a non-finite sensor, floor(a1 - a2)
+    double bu_bl;    // LAD: (double)(B_u - B_l) (host-converted)
     double a1, a2;   // TENO5-A: alpha_1, alpha_2 of eq 2.16
     double cr;       // TENO5-A: C_r of eq 2.17
     double epsA;     // TENO5-A: 0.9 C_r / (1 - 0.9 C_r) xi^2 of eq 2.18 (host-evaluated)
@@ -247,6 +248,11 @@ struct DecisionConsts {
     // largest cutoff ct_hi: all three stencils are kept, whatever the ladder
     // index.  Negative: no such bound (never satisfied).
     double smooth_t;
+    // host products of the margins below: ct_hi (1 + margin), ct_lo (1 -
+    // margin) and margin |xthr[j]| (kept out of the kernels' loops, where the
+    // compiler would re-form them for every characteristic field)
+    double hi_fac, lo_fac;
+    double xmarg[kMaxThr];
 };
 
 // Relative margin inside which an approximate decision value is not trusted
@@ -317,7 +323,7 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
         if (t2 > x) x = t2;
         const double theta = cr_div(1.0, 1.0 + cr_div(x, S.H));
         if (theta >= 0.0)
-            m = S.Bl + (int)floor(theta * (double)(S.Bu - S.Bl));
+            m = S.Bl + (int)floor(theta * S.bu_bl);
         else
             m = S.Bl;
         ct = kLadder[m];
@@ -396,8 +402,8 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
                 chi_hi = chi_lo = teno5a_cutoff(S, a, b, c, d, e, &kA);
                 m = (uint32_t)kA;
             }
-            const double hi = chi_hi * (1.0 + kDecisionMargin) * sum;
-            const double lo = chi_lo * (1.0 - kDecisionMargin) * sum;
+            const double hi = (A5 ? chi_hi * (1.0 + kDecisionMargin) : K.hi_fac) * sum;
+            const double lo = (A5 ? chi_lo * (1.0 - kDecisionMargin) : K.lo_fac) * sum;
             const bool k0 = g0 >= hi, k1 = g1 >= hi, k2 = g2 >= hi;
             const bool c0 = g0 < lo, c1 = g1 < lo, c2 = g2 < lo;
             sure = isfinite(sum) && (k0 || c0) && (k1 || c1) && (k2 || c2);
@@ -413,7 +419,7 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
                 for (int j = 0; j < kMaxThr; ++j) {
                     const double T = K.xthr[j];
                     above += (x <= T) ? 1u : 0u;
-                    msure = msure && (fabs(x - T) > kDecisionMargin * fabs(T));
+                    msure = msure && (fabs(x - T) > K.xmarg[j]);
                 }
                 m = (uint32_t)S.Bl + above;
                 if (!sure) {

@@ -51,6 +51,7 @@ inline SchemeParams scheme_of(const teno_grid* g) {
     s.scheme = g->scheme;
     s.Bl = g->Bl;
     s.Bu = g->Bu;
+    s.bu_bl = (double)(g->Bu - g->Bl);
     s.a1 = g->a1;
     s.a2 = g->a2;
     s.cr = g->cr;
@@ -92,7 +93,18 @@ inline double smooth_bound(double ct) {
     return T > 0.0 ? T : -1.0;
 }
 
+inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m);
+
+// Decision constants with the host-side margin products filled in.
 inline DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
+    DecisionConsts K = decision_consts_base(g, need_m);
+    K.hi_fac = K.ct_hi * (1.0 + kDecisionMargin);
+    K.lo_fac = K.ct_lo * (1.0 - kDecisionMargin);
+    for (int j = 0; j < kMaxThr; ++j) K.xmarg[j] = kDecisionMargin * std::fabs(K.xthr[j]);
+    return K;
+}
+
+inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m) {
     DecisionConsts K;
     memset(&K, 0, sizeof(K));
     K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;

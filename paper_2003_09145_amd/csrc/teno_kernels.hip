@@ -111,8 +111,15 @@ __device__ __forceinline__ unsigned long long mask_hash(unsigned long long z) {
 // CAPC: the stencil-buffer stride when it is known at compile time (it is
 // ext_cap_for(n) = 74 for every n >= 63), so that every LDS stencil read is a
 // per-lane base plus an immediate offset; 0: taken from A.ext_cap.
+// kCapBlockLong: the x-sweep window of 4 chunks when lines hold n >= 252
+// cells (253 faces then span at most 2 lines: 252 + 6 + 5 = 263 cells); its
+// 31.1 KB of LDS let 5 blocks share a CU, so it is compiled for 5 waves per
+// SIMD (at most 96 VGPRs).
+constexpr int kCapBlockLong = 264;
+
 template <int ND, int DIR, int W, bool DIGEST, int CAPC, bool A5>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs A) {
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(CAPC == kCapBlockLong ? 5 : 4))) void k_sweep(SweepArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
@@ -624,6 +631,13 @@ static hipError_t launch_sweep_t(SweepArgs A, bool digest, hipStream_t st) {
     // neighbouring columns, which needs whole blocks of columns (8- and
     // 16-column blocks, with 71 / 142 KB of LDS, measured no faster)
     if constexpr (DIR == 0) {
+        if (!digest && A.ext_cap == kCapLong && A.n >= 252) {
+            const int64_t blocks = (A.nchunks + 3) / 4;
+            hipLaunchKernelGGL((k_sweep<ND, DIR, 4, false, kCapBlockLong, A5>),
+                               dim3((unsigned)blocks), dim3(256),
+                               table + (size_t)NV * kCapBlockLong * sizeof(double), st, A);
+            return hipGetLastError();
+        }
         if (!digest && A.ext_cap == kCapLong) {
             // x: 4 consecutive chunks per block staged once as the union of
             // their windows (4 x 63 faces span at most 5 lines when n >= 63:
