@@ -793,6 +793,7 @@ def summarize_counters(d):
     calf = _read_counters(os.path.join(d, "calf"))
     calw = _read_counters(os.path.join(d, "calw"))
     valu = _read_counters(os.path.join(d, "valu"))
+    mix = _read_counters(os.path.join(d, "mix")) if os.path.isdir(os.path.join(d, "mix")) else {}
 
     def copy_kib(tab, counter):
         best = None
@@ -821,6 +822,10 @@ def summarize_counters(d):
         "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVES "
         "--output-format csv -d $OUT/valu -o valu -- python3 bench.py --steps 5 "
         "--warmup 1 --no-cpu-baseline --no-extras",
+        "#   rocprofv3 --pmc SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_CVT "
+        "SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAIT_INST_LDS SQ_WAIT_INST_ANY SQ_INSTS_VALU_FLOPS_FP64 "
+        "--output-format csv -d $OUT/mix -o mix -- python3 bench.py --steps 5 --warmup 1 "
+        "--no-cpu-baseline --no-extras",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/calf -o calf -- "
         "python3 bench.py --copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/calw -o calw -- "
@@ -871,6 +876,34 @@ def summarize_counters(d):
                      f"active_inst_valu={g('SQ_ACTIVE_INST_VALU'):.0f}, "
                      f"busy_cycles={g('SQ_BUSY_CYCLES'):.0f}, executed_f64_flop={flop:.4e}, "
                      f"algorithmic_flop={alg:.4e}")
+    if mix:
+        lines.append("#")
+        lines.append("# instruction mix per wave (wave-level instruction counts / SQ_WAVES of the valu")
+        lines.append("# pass; other VALU = all VALU - FP64 arithmetic - INT32 - INT64 - CVT: compares,")
+        lines.append("# selects, moves, exponent/mantissa operations and lane reads/writes)")
+        for k in sorted(mix):
+            sk = _short(k)
+            if not sk.startswith("k_sweep<3"):
+                continue
+            waves = None
+            for kk, cs in valu.items():
+                if _short(kk) == sk:
+                    waves = cs.get("SQ_WAVES", (0.0, 0))[0]
+                    g = lambda c: cs.get(c, (0.0, 0))[0]
+                    f64 = (g("SQ_INSTS_VALU_ADD_F64") + g("SQ_INSTS_VALU_MUL_F64") +
+                           g("SQ_INSTS_VALU_FMA_F64") + g("SQ_INSTS_VALU_TRANS_F64"))
+                    allv = g("SQ_INSTS_VALU")
+            if not waves:
+                continue
+            m = lambda c: mix[k].get(c, (0.0, 0))[0] / waves
+            other = allv / waves - f64 / waves - m("SQ_INSTS_VALU_INT32") - m(
+                "SQ_INSTS_VALU_INT64") - m("SQ_INSTS_VALU_CVT")
+            lines.append(f"mix {sk}: valu={allv / waves:.0f}, fp64={f64 / waves:.0f}, "
+                         f"int32={m('SQ_INSTS_VALU_INT32'):.0f}, int64={m('SQ_INSTS_VALU_INT64'):.0f}, "
+                         f"cvt={m('SQ_INSTS_VALU_CVT'):.0f}, other_valu={other:.0f}, "
+                         f"lds={m('SQ_INSTS_LDS'):.0f}, salu={m('SQ_INSTS_SALU'):.0f}, "
+                         f"wait_inst_lds={m('SQ_WAIT_INST_LDS'):.0f}, "
+                         f"wait_inst_any={m('SQ_WAIT_INST_ANY'):.0f}")
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
         f.write("\n".join(lines) + "\n")

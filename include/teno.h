@@ -268,6 +268,13 @@ int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
  * U; these entry points apply the transpose of its Jacobian A(U) = dL/dU and
  * of one SSP-RK3 step.  The flags are recomputed from U with the forward
  * arithmetic, so they are exactly the forward pass's.
+ *
+ * What is differentiated is the fixed-step map: the time step dt_n and the
+ * per-stage speeds alpha_{n,s} are inputs (recorded by the forward run), not
+ * functions of U.  Both are maxima over cells of |u_d| + c, so they depend on
+ * U only through the cell that attains the maximum; that derivative is not
+ * included.  A finite-difference check must replay the recorded dt and
+ * speeds (teno_ctrl_replay) to see the same map.
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes for teno_rhs_adjoint / teno_step_adjoint: six state-sized
