@@ -994,7 +994,9 @@ def summarize_adjoint_trace(d, log=None):
         lines.append(f"{name[:58]:58s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f}")
     if log:
-        b = json.loads(open(log).read().strip().splitlines()[-1])["adjoint_3d"]
+        # the run's JSON line (the log may also hold the profiler's messages)
+        js = [ln for ln in open(log).read().splitlines() if ln.startswith('{"adjoint_3d"')]
+        b = json.loads(js[-1])["adjoint_3d"]
         lines += ["#", "# HIP events around 5 calls each in the same run:",
                   f"#   teno_rhs {b['rhs_ms']:.4f} ms, teno_rhs_adjoint {b['rhs_adjoint_ms']:.4f} ms, "
                   f"ratio {b['rhs_adjoint_over_rhs']:.3f}"]
