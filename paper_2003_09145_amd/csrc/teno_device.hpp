@@ -373,15 +373,22 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
         bool sure = K.literal == 0;
         uint32_t m = 0, mask = 7u;
         const double tau = fabs(beta2 - beta0);
-        double bmin = beta0 < beta1 ? beta0 : beta1;
-        bmin = beta2 < bmin ? beta2 : bmin;
-        if (sure && K.need_m == 0 && tau <= K.smooth_t * (bmin + S.eps)) {
+        const double be0 = beta0 + S.eps, be1 = beta1 + S.eps, be2 = beta2 + S.eps;
+        // Smooth test tau <= smooth_t (min_k beta_k + eps), one compare per
+        // stencil: x -> RN(x + eps) and x -> RN(smooth_t x) are monotone
+        // (smooth_t > 0; a negative smooth_t fails every form), so the rounded
+        // bound at the smallest beta_k is the smallest of the three bounds.
+        // A NaN beta_k fails its compare, and it needs a NaN stencil value,
+        // which makes beta_0 or beta_2 NaN and so tau NaN as well.
+        const bool smooth = tau <= K.smooth_t * be0 && tau <= K.smooth_t * be1 &&
+                            tau <= K.smooth_t * be2;
+        if (sure && K.need_m == 0 && smooth) {
             // smooth stencil: all kept (no reciprocal, no gamma_k)
         } else if (sure) {
             // Approximate gamma_k (eq 2.8) from approximate chi~_k = tau / (beta_k + eps).
-            const double t0 = tau * rcp_nr(beta0 + S.eps);
-            const double t1 = tau * rcp_nr(beta1 + S.eps);
-            const double t2 = tau * rcp_nr(beta2 + S.eps);
+            const double t0 = tau * rcp_nr(be0);
+            const double t1 = tau * rcp_nr(be1);
+            const double t2 = tau * rcp_nr(be2);
             double y, y2;
             y = 1.0 + t0;
             y2 = y * y;
