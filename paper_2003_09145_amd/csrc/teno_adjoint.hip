@@ -51,6 +51,13 @@ __device__ __forceinline__ double cand_coef(const double* w, int m) {
     }
 }
 
+// The reverse-mode arithmetic below is not held to the forward path's
+// bit-for-bit order (its bar is a relative error against the oracle's forward
+// mode), so its sums of products are fused multiply-adds.
+__device__ __forceinline__ double fmad(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
+
 struct AdjArgs {
     const double* U;
     const double* lam;
@@ -65,7 +72,7 @@ struct AdjArgs {
 };
 
 template <int ND, int DIR, bool A5>
-__global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_chunk(AdjArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
@@ -75,8 +82,11 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
     double* omega = smem;       // 24: eq 2.15 weights per cutoff mask
     double* ctab = smem + 24;   // 40: cand_coef per (mask, stencil value)
     double* ext = smem + 64;    // NV x cap staged rows (forward quantities)
-    double* acc = ext + (size_t)NV * cap;  // NV x cap cotangents: F (NC, local),
-                                           // U (NC, local), sqrt(rho), u (ND), H
+    // NV x cap cotangents: F (NC, local), U (NC, local), sqrt(rho), u (ND), H.
+    // They reuse the staged rows: every read of those rows comes first in
+    // program order, and the chunk is one wave, whose LDS operations
+    // complete in order.
+    double* acc = ext;
     const int lane = threadIdx.x;
     if (lane < 24) omega[lane] = kOmega[lane / 3][lane % 3];
     if (lane < 40) ctab[lane] = cand_coef(&kOmega[lane / 5][0], lane % 5);
@@ -116,11 +126,18 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
             if (idx < count) load_ext(idx, qn, &fn);
             if (flip) q[1 + DIR] = -q[1 + DIR];
             stage_cell<ND, DIR>(q, alpha, gm1, ext, cap, cur);
-#pragma unroll
-            for (int r = 0; r < NV; ++r) acc[(size_t)r * cap + cur] = 0.0;
         }
     }
     __syncthreads();
+
+    // Per face, held from the read phase to the accumulation phase: the
+    // frozen masks, nu = R^T mu, the left eigenvector rows (formed after the
+    // read phase's peak), and the Roe cotangents of the face's two cells
+    // (sqrt(rho), u, H of cells o+2, o+3).
+    uint32_t masks = 0;
+    double nu[NC];
+    double Lrow[NC][NC];
+    double roe_l[ND + 2], roe_r[ND + 2];
 
     if (valid) {
         // cotangent of the face flux (local order)
@@ -141,7 +158,8 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         double ut_b[ND > 1 ? ND - 1 : 1];
 #pragma unroll
         for (int kk = 0; kk < ND - 1; ++kk) ut_b[kk] = 0.0;
-        uint32_t masks = 0;
+        const double csm = R.cs * mul[NC - 1];      // acoustic terms of R^T mu
+        const double m1u = fmad(R.un, mul[NC - 1], mul[1]);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             double Lr[NC];
@@ -156,47 +174,43 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
                 fh = sg ? fh + r : r;
             }
             if (s == 0 || s == NC - 1) {
-                const double sgn = (s == 0) ? -1.0 : 1.0;
-                un_b += mul[1] * fh + sgn * R.cs * mul[NC - 1] * fh;
-                cs_b += sgn * mul[1] * fh + sgn * R.un * mul[NC - 1] * fh;
-                Hb_b += mul[NC - 1] * fh;
+                // d/d(un, cs, Hb) of mu . R[:, s] fh with R[:, s] = (1, un -+ cs,
+                // ut, Hb -+ un cs)
+                const double sfh = (s == 0) ? -fh : fh;
+                un_b = fmad(mul[1], fh, fmad(csm, sfh, un_b));
+                cs_b = fmad(m1u, sfh, cs_b);
+                Hb_b = fmad(mul[NC - 1], fh, Hb_b);
 #pragma unroll
-                for (int kk = 1; kk < ND; ++kk) ut_b[kk - 1] += mul[1 + kk] * fh;
+                for (int kk = 1; kk < ND; ++kk) ut_b[kk - 1] = fmad(mul[1 + kk], fh, ut_b[kk - 1]);
             } else if (s == 1) {
-                un_b += mul[1] * fh;
-                q2_b += 0.5 * mul[NC - 1] * fh;
+                un_b = fmad(mul[1], fh, un_b);
+                q2_b = fmad(0.5 * mul[NC - 1], fh, q2_b);
 #pragma unroll
-                for (int kk = 1; kk < ND; ++kk) ut_b[kk - 1] += mul[1 + kk] * fh;
+                for (int kk = 1; kk < ND; ++kk) ut_b[kk - 1] = fmad(mul[1 + kk], fh, ut_b[kk - 1]);
             } else {
 #pragma unroll
                 for (int kk = 1; kk < ND; ++kk)
-                    if (s == 1 + kk) ut_b[kk - 1] += mul[NC - 1] * fh;
+                    if (s == 1 + kk) ut_b[kk - 1] = fmad(mul[NC - 1], fh, ut_b[kk - 1]);
             }
         }
 
         // nu_s = (R^T mu)_s: the cotangent of the characteristic flux fh_s
-        double nu[NC];
         {
-            double tsum = 0.0;
+            double t0 = mul[0];  // mu_0 + ut . mu_t
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) tsum += R.ut[kk - 1] * mul[1 + kk];
-            nu[0] = mul[0] + (R.un - R.cs) * mul[1] + tsum + (R.Hb - R.unc) * mul[NC - 1];
-            nu[1] = mul[0] + R.un * mul[1] + tsum + R.hq2 * mul[NC - 1];
-            nu[NC - 1] = mul[0] + (R.un + R.cs) * mul[1] + tsum + (R.Hb + R.unc) * mul[NC - 1];
+            for (int kk = 1; kk < ND; ++kk) t0 = fmad(R.ut[kk - 1], mul[1 + kk], t0);
+            nu[0] = fmad(R.Hb - R.unc, mul[NC - 1], fmad(R.un - R.cs, mul[1], t0));
+            nu[1] = fmad(R.hq2, mul[NC - 1], fmad(R.un, mul[1], t0));
+            nu[NC - 1] = fmad(R.Hb + R.unc, mul[NC - 1], fmad(R.un + R.cs, mul[1], t0));
 #pragma unroll
-            for (int kk = 1; kk < ND; ++kk) nu[1 + kk] = mul[1 + kk] + R.ut[kk - 1] * mul[NC - 1];
+            for (int kk = 1; kk < ND; ++kk) nu[1 + kk] = fmad(R.ut[kk - 1], mul[NC - 1], mul[1 + kk]);
         }
-        double Lrow[NC][NC];
-#pragma unroll
-        for (int s = 0; s < NC; ++s) left_row<ND>(R, s, Lrow[s]);
-
         // Stencil cell j of the face (0 .. 5 = i-2 .. i+3): the reconstruction
         // of f+ holds it as value j (j <= 4), that of f- as value 5 - j
-        // (j >= 1).  a_s, b_s are the cotangents of those projected values;
-        // the split-flux cotangents are L^T a and L^T b, added to the cell's
-        // accumulators as F-bar = (f+bar + f-bar)/2 and U-bar = alpha (f+bar -
-        // f-bar)/2.  Lanes hold distinct cells at each j, and a wave's LDS
-        // operations complete in order, so the sums need no atomics.
+        // (j >= 1).  a_s, b_s are the cotangents of those projected values.
+        // Read phase: the cotangent of the left eigenvector entries,
+        // sum over j of f+_j a_s + f-_j b_s (the split-flux cotangents L^T a
+        // and L^T b are added to the cells in the accumulation phase below).
         double Lb[NC][NC];  // cotangent of the left eigenvector entries
 #pragma unroll
         for (int s = 0; s < NC; ++s)
@@ -212,65 +226,47 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
                 a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
                 b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
             }
-            double* cf = acc + o + j;
             const double* fpj = ext + o + j;
             const double* fmj = ext + (size_t)NC * cap + o + j;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                double pb = 0.0, mb = 0.0;
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-                    if (!shear) {
-                        pb += Lrow[s][c] * a[s];
-                        mb += Lrow[s][c] * b[s];
-                    } else if (c == 0) {
-                        pb += Lrow[s][0] * a[s];
-                        mb += Lrow[s][0] * b[s];
-                    } else if (c == s) {
-                        pb += a[s];
-                        mb += b[s];
-                    }
-                }
-                cf[(size_t)c * cap] += 0.5 * (pb + mb);
-                cf[(size_t)(NC + c) * cap] += (0.5 * alpha) * (pb - mb);
                 const double fp = fpj[(size_t)c * cap], fm = fmj[(size_t)c * cap];
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-                    if (!shear || c == 0) Lb[s][c] += fp * a[s] + fm * b[s];
+                    if (!shear || c == 0) Lb[s][c] = fmad(fp, a[s], fmad(fm, b[s], Lb[s][c]));
                 }
             }
-            __asm__ __volatile__("" ::: "memory");
         }
 
         // left eigenvector entries -> Roe scalars
         {
             const double a00 = Lb[0][0], a01 = Lb[0][1], l00 = Lb[NC - 1][0], l01 = Lb[NC - 1][1];
-            b2_b += 0.5 * a00 + 0.5 * l00 - Lb[1][0];
-            un_b += 0.5 * R.ci * (a00 - l00) - 0.5 * R.b1 * (a01 + l01) + R.b1 * Lb[1][1];
-            ci_b += 0.5 * R.un * (a00 - l00) - 0.5 * a01 + 0.5 * l01;
-            b1_b += -0.5 * R.un * (a01 + l01) + R.un * Lb[1][1] +
-                    0.5 * (Lb[0][NC - 1] + Lb[NC - 1][NC - 1]) - Lb[1][NC - 1];
+            const double dA = 0.5 * (a00 - l00), sA = 0.5 * (a01 + l01);
+            b2_b += fmad(0.5, a00 + l00, -Lb[1][0]);
+            un_b = fmad(R.ci, dA, fmad(R.b1, Lb[1][1] - sA, un_b));
+            ci_b = fmad(R.un, dA, ci_b + 0.5 * (l01 - a01));
+            b1_b = fmad(R.un, Lb[1][1] - sA,
+                        b1_b + fmad(0.5, Lb[0][NC - 1] + Lb[NC - 1][NC - 1], -Lb[1][NC - 1]));
 #pragma unroll
             for (int kk = 1; kk < ND; ++kk) {
-                const double t = -0.5 * (Lb[0][1 + kk] + Lb[NC - 1][1 + kk]) + Lb[1][1 + kk];
-                b1_b += R.ut[kk - 1] * t;
-                ut_b[kk - 1] += R.b1 * t - Lb[1 + kk][0];
+                const double t = fmad(-0.5, Lb[0][1 + kk] + Lb[NC - 1][1 + kk], Lb[1][1 + kk]);
+                b1_b = fmad(R.ut[kk - 1], t, b1_b);
+                ut_b[kk - 1] += fmad(R.b1, t, -Lb[1 + kk][0]);
             }
         }
         // derived scalars: b2 = b1 q2 / 2, b1 = gm1 / c2, ci = 1 / cs, cs = sqrt(c2),
         // c2 = gm1 (Hb - q2 / 2), q2 = |ub|^2
-        q2_b += 0.5 * R.b1 * b2_b;
-        b1_b += 0.5 * R.q2 * b2_b;
-        double c2_b = -(R.b1 / R.c2) * b1_b;
-        cs_b += -(R.ci * R.ci) * ci_b;
-        c2_b += cs_b / (2.0 * R.cs);
-        Hb_b += gm1 * c2_b;
-        q2_b += -0.5 * gm1 * c2_b;
+        q2_b = fmad(0.5 * R.b1, b2_b, q2_b);
+        b1_b = fmad(0.5 * R.q2, b2_b, b1_b);
+        cs_b = fmad(-(R.ci * R.ci), ci_b, cs_b);
+        // c2_b = -(b1 / c2) b1_b + cs_b / (2 cs), with 1 / cs = ci
+        const double c2_b = fmad(-(R.b1 / R.c2), b1_b, (0.5 * R.ci) * cs_b);
+        Hb_b = fmad(gm1, c2_b, Hb_b);
+        q2_b = fmad(-0.5 * gm1, c2_b, q2_b);
         double ub_b[ND];
 #pragma unroll
-        for (int kk = 0; kk < ND; ++kk) ub_b[kk] = 2.0 * R.ub[kk] * q2_b;
+        for (int kk = 0; kk < ND; ++kk) ub_b[kk] = (2.0 * R.ub[kk]) * q2_b;
         ub_b[DIR] += un_b;
 #pragma unroll
         for (int kk = 1; kk < ND; ++kk) ub_b[LO::tan_axis(kk)] += ut_b[kk - 1];
@@ -278,7 +274,7 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         const double* uu = ext + (size_t)(2 * NC + 1) * cap;
         const double* hh = ext + (size_t)(2 * NC + 1 + ND) * cap;
         const double w = R.wsum, rl = R.rl, rr = R.rr;
-        const double SH = rl * hh[o + 2] + rr * hh[o + 3];
+        const double SH = fmad(rl, hh[o + 2], rr * hh[o + 3]);
         double w_b = SH * Hb_b;
         const double SH_b = w * Hb_b;
         double rl_b = hh[o + 2] * SH_b, rr_b = hh[o + 3] * SH_b;
@@ -286,25 +282,81 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk) {
             const double u2 = uu[(size_t)kk * cap + o + 2], u3 = uu[(size_t)kk * cap + o + 3];
-            w_b += (rl * u2 + rr * u3) * ub_b[kk];
+            w_b = fmad(fmad(rl, u2, rr * u3), ub_b[kk], w_b);
             const double Sk_b = w * ub_b[kk];
             ul_b[kk] = rl * Sk_b;
             ur_b[kk] = rr * Sk_b;
-            rl_b += u2 * Sk_b;
-            rr_b += u3 * Sk_b;
+            rl_b = fmad(u2, Sk_b, rl_b);
+            rr_b = fmad(u3, Sk_b, rr_b);
         }
-        rl_b += -(w * w) * w_b;
-        rr_b += -(w * w) * w_b;
+        rl_b = fmad(-(w * w), w_b, rl_b);
+        rr_b = fmad(-(w * w), w_b, rr_b);
+        roe_l[0] = rl_b;
+        roe_r[0] = rr_b;
+#pragma unroll
+        for (int kk = 0; kk < ND; ++kk) {
+            roe_l[1 + kk] = ul_b[kk];
+            roe_r[1 + kk] = ur_b[kk];
+        }
+        roe_l[1 + ND] = rl * SH_b;
+        roe_r[1 + ND] = rr * SH_b;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) left_row<ND>(R, s, Lrow[s]);
+    }
+    // every read of the staged rows is above: clear the cotangent rows
+    for (int idx = lane; idx < count; idx += 64) {
+#pragma unroll
+        for (int r = 0; r < NV; ++r) acc[(size_t)r * cap + idx] = 0.0;
+    }
+    // the accumulation phase re-reads the coefficient table rather than
+    // holding the read phase's values in registers
+    __asm__ __volatile__("" ::: "memory");
+    if (valid) {
+        // Accumulation phase: L^T a and L^T b added to the stencil cells as
+        // F-bar = (f+bar + f-bar)/2 and U-bar = alpha (f+bar - f-bar)/2.
+        // Lanes hold distinct cells at each j, and a wave's LDS operations
+        // complete in order, so the sums need no atomics.
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
+            double a[NC], b[NC];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
+                a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
+                b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
+            }
+            double* cf = acc + o + j;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double pb = 0.0, mb = 0.0;
+#pragma unroll
+                for (int s = 0; s < NC; ++s) {
+                    const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+                    if (!shear) {
+                        pb = fmad(Lrow[s][c], a[s], pb);
+                        mb = fmad(Lrow[s][c], b[s], mb);
+                    } else if (c == 0) {
+                        pb = fmad(Lrow[s][0], a[s], pb);
+                        mb = fmad(Lrow[s][0], b[s], mb);
+                    } else if (c == s) {
+                        pb += a[s];
+                        mb += b[s];
+                    }
+                }
+                cf[(size_t)c * cap] = fmad(0.5, pb + mb, cf[(size_t)c * cap]);
+                cf[(size_t)(NC + c) * cap] =
+                    fmad(0.5 * alpha, pb - mb, cf[(size_t)(NC + c) * cap]);
+            }
+            __asm__ __volatile__("" ::: "memory");
+        }
+        // Roe cotangents of the face's two cells
         double* cr = acc + (size_t)(2 * NC) * cap + o;
-        cr[2] += rl_b;
-        cr[(size_t)(1 + ND) * cap + 2] += rl * SH_b;
 #pragma unroll
-        for (int kk = 0; kk < ND; ++kk) cr[(size_t)(1 + kk) * cap + 2] += ul_b[kk];
+        for (int r = 0; r < ND + 2; ++r) cr[(size_t)r * cap + 2] += roe_l[r];
         __asm__ __volatile__("" ::: "memory");
-        cr[3] += rr_b;
-        cr[(size_t)(1 + ND) * cap + 3] += rr * SH_b;
 #pragma unroll
-        for (int kk = 0; kk < ND; ++kk) cr[(size_t)(1 + kk) * cap + 3] += ur_b[kk];
+        for (int r = 0; r < ND + 2; ++r) cr[(size_t)r * cap + 3] += roe_r[r];
     }
     // the first staged cell of the per-cell phase is loaded before the barrier
     int idx3 = lane;
@@ -323,14 +375,16 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         idx3 += 64;
         if (idx3 < count) load_ext(idx3, qn3, &fn3);
         if (flip) q[1 + DIR] = -q[1 + DIR];
-        const double rho = q[0], ri = 1.0 / rho, E = q[NC - 1];
+        // the cell's primitives to a few ulp (reciprocal and reciprocal square
+        // root refined by Newton steps; the adjoint is held to a relative bar)
+        const double rho = q[0], ri = rcp_nr(rho), E = q[NC - 1];
         double u[ND], uu2 = 0.0;
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk) {
             u[kk] = q[1 + kk] * ri;
-            uu2 += u[kk] * u[kk];
+            uu2 = fmad(u[kk], u[kk], uu2);
         }
-        const double p = gm1 * (E - 0.5 * rho * uu2);
+        const double p = gm1 * fmad(-0.5 * rho, uu2, E);
         const double H = (E + p) * ri;
         double Fb[NC], gq[NC];
 #pragma unroll
@@ -351,29 +405,33 @@ __global__ __launch_bounds__(64) void k_adj_chunk(AdjArgs A) {
         m_b[DIR] += Fb[0];
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk) {
-            m_b[kk] += u[DIR] * Fb[1 + kk];
-            u_b[DIR] += q[1 + kk] * Fb[1 + kk];
+            m_b[kk] = fmad(u[DIR], Fb[1 + kk], m_b[kk]);
+            u_b[DIR] = fmad(q[1 + kk], Fb[1 + kk], u_b[DIR]);
         }
         p_b += Fb[1 + DIR];
-        E_b += u[DIR] * Fb[NC - 1];
-        p_b += u[DIR] * Fb[NC - 1];
-        u_b[DIR] += (E + p) * Fb[NC - 1];
+        E_b = fmad(u[DIR], Fb[NC - 1], E_b);
+        p_b = fmad(u[DIR], Fb[NC - 1], p_b);
+        u_b[DIR] = fmad(E + p, Fb[NC - 1], u_b[DIR]);
         // H = (E + p) / rho
-        E_b += H_b * ri;
-        p_b += H_b * ri;
-        rho_b += -H * H_b * ri;
-        // sqrt(rho)
-        rho_b += sr_b / (2.0 * sqrt(rho));
+        const double Hr = H_b * ri;
+        E_b += Hr;
+        p_b += Hr;
+        rho_b = fmad(-H, Hr, rho_b);
+        // sqrt(rho): d sqrt(rho) / d rho = rsqrt(rho) / 2
+        double y = __builtin_amdgcn_rsq(rho);
+        y = y * fmad(-0.5 * rho, y * y, 1.5);
+        y = y * fmad(-0.5 * rho, y * y, 1.5);
+        rho_b = fmad(sr_b, 0.5 * y, rho_b);
         // p = (gamma - 1) (E - |m|^2 / (2 rho))
-        E_b += gm1 * p_b;
-        rho_b += 0.5 * gm1 * uu2 * p_b;
+        E_b = fmad(gm1, p_b, E_b);
+        rho_b = fmad(0.5 * gm1 * uu2, p_b, rho_b);
 #pragma unroll
-        for (int kk = 0; kk < ND; ++kk) m_b[kk] += -gm1 * u[kk] * p_b;
+        for (int kk = 0; kk < ND; ++kk) m_b[kk] = fmad(-gm1 * u[kk], p_b, m_b[kk]);
         // u_k = m_k / rho
 #pragma unroll
         for (int kk = 0; kk < ND; ++kk) {
-            m_b[kk] += u_b[kk] * ri;
-            rho_b += -u[kk] * u_b[kk] * ri;
+            m_b[kk] = fmad(u_b[kk], ri, m_b[kk]);
+            rho_b = fmad(-u[kk] * ri, u_b[kk], rho_b);
         }
         gq[0] += rho_b;
 #pragma unroll
@@ -459,7 +517,7 @@ template <int ND, int DIR>
 static hipError_t launch_adj(AdjArgs A, hipStream_t st) {
     constexpr int NV = 2 * (ND + 2) + ND + 2;
     const int64_t nblk = A.G.kchunks * A.G.ncols;
-    const size_t lds = (size_t)(64 + 2 * NV * A.G.cap) * sizeof(double);
+    const size_t lds = (size_t)(64 + NV * A.G.cap) * sizeof(double);
     if (A.sch.scheme == TENO_SCHEME_TENO5A)
         hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true>), dim3((unsigned)nblk), dim3(64), lds, st, A);
     else
