@@ -58,6 +58,143 @@ __device__ __forceinline__ double fmad(double a, double b, double c) {
     return __builtin_fma(a, b, c);
 }
 
+// Derivatives of the all-kept (mask 7) reconstruction with respect to its
+// stencil values v_0 .. v_4: cand_coef on the mask-7 weights.
+__device__ __forceinline__ constexpr double lin_coef(int m) {
+    return m == 0   ? omega_of(7, 0) * (1.0 / 3.0)
+           : m == 1 ? -(omega_of(7, 0) * (7.0 / 6.0)) - omega_of(7, 1) * (1.0 / 6.0)
+           : m == 2 ? (omega_of(7, 0) * (11.0 / 6.0) + omega_of(7, 1) * (5.0 / 6.0)) +
+                          omega_of(7, 2) * (1.0 / 3.0)
+           : m == 3 ? omega_of(7, 1) * (1.0 / 3.0) + omega_of(7, 2) * (5.0 / 6.0)
+                    : -(omega_of(7, 2) * (1.0 / 6.0));
+}
+
+// Reverse sums of one face over its stencil cells j = 0 .. 5 (cells i-2 ..
+// i+3).  The reconstruction of f+ holds cell j as value j (j <= 4), that of
+// f- as value 5 - j (j >= 1); a_s, b_s are the cotangents of those projected
+// values of characteristic field s: nu_s times the derivative of the
+// frozen-weight reconstruction.  LM (compile time): the fields whose masks
+// are 7 for both signs on every face of the wave; their reconstruction is the
+// linear one for all of them, so their part of the sums factors through one
+// linear reconstruction per component (rev_read) and through
+// g = sum_s L[s, :] nu_s (rev_acc).
+template <int ND, int LM>
+__device__ __forceinline__ void rev_read(const double* __restrict__ ext, int cap, int o,
+                                         uint32_t masks, const double (&nu)[ND + 2],
+                                         const double* __restrict__ ctab,
+                                         double (&Lb)[ND + 2][ND + 2]) {
+    constexpr int NC = ND + 2;
+    // Lb[s][c] = sum_j f+_j[c] a_s + f-_j[c] b_s: the cotangent of the left
+    // eigenvector entries
+    double h[NC];  // linear reconstruction of f+ and f- per component
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Lb[s][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
+        double a[NC], b[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            if (LM & (1 << s)) continue;
+            const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
+            a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
+            b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
+        }
+        const double* fpj = ext + o + j;
+        const double* fmj = ext + (size_t)NC * cap + o + j;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double fp = fpj[(size_t)c * cap], fm = fmj[(size_t)c * cap];
+            if (LM != 0) {
+                if (j <= 4) h[c] = fmad(lin_coef(jp), fp, h[c]);
+                if (j >= 1) h[c] = fmad(lin_coef(jm), fm, h[c]);
+            }
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                if (LM & (1 << s)) continue;
+                const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+                if (!shear || c == 0) Lb[s][c] = fmad(fp, a[s], fmad(fm, b[s], Lb[s][c]));
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (!(LM & (1 << s))) continue;
+        const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (!shear || c == 0) Lb[s][c] = nu[s] * h[c];
+    }
+}
+
+// Accumulation of L^T a and L^T b into the stencil cells' cotangent rows as
+// F-bar = (f+bar + f-bar)/2 and U-bar = alpha (f+bar - f-bar)/2.  Lanes hold
+// distinct cells at each j, and a wave's LDS operations complete in order,
+// so the sums need no atomics.
+template <int ND, int LM>
+__device__ __forceinline__ void rev_acc(double* __restrict__ acc, int cap, int o, uint32_t masks,
+                                        const double (&nu)[ND + 2],
+                                        const double (&Lrow)[ND + 2][ND + 2],
+                                        const double* __restrict__ ctab, double alpha) {
+    constexpr int NC = ND + 2;
+    double g[NC];  // sum over the linear fields of L[s, :] nu_s
+#pragma unroll
+    for (int c = 0; c < NC; ++c) g[c] = 0.0;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (!(LM & (1 << s))) continue;
+        const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+        if (!shear) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) g[c] = fmad(Lrow[s][c], nu[s], g[c]);
+        } else {
+            g[0] = fmad(Lrow[s][0], nu[s], g[0]);
+            g[s] += nu[s];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
+        const double cp = (j <= 4) ? lin_coef(jp) : 0.0, cm = (j >= 1) ? lin_coef(jm) : 0.0;
+        double a[NC], b[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            if (LM & (1 << s)) continue;
+            const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
+            a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
+            b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
+        }
+        double* cf = acc + o + j;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double pb = (LM != 0 && j <= 4) ? cp * g[c] : 0.0;
+            double mb = (LM != 0 && j >= 1) ? cm * g[c] : 0.0;
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                if (LM & (1 << s)) continue;
+                const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+                if (!shear) {
+                    pb = fmad(Lrow[s][c], a[s], pb);
+                    mb = fmad(Lrow[s][c], b[s], mb);
+                } else if (c == 0) {
+                    pb = fmad(Lrow[s][0], a[s], pb);
+                    mb = fmad(Lrow[s][0], b[s], mb);
+                } else if (c == s) {
+                    pb += a[s];
+                    mb += b[s];
+                }
+            }
+            cf[(size_t)c * cap] = fmad(0.5, pb + mb, cf[(size_t)c * cap]);
+            cf[(size_t)(NC + c) * cap] = fmad(0.5 * alpha, pb - mb, cf[(size_t)(NC + c) * cap]);
+        }
+        __asm__ __volatile__("" ::: "memory");
+    }
+}
+
 struct AdjArgs {
     const double* U;
     const double* lam;
@@ -138,6 +275,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double nu[NC];
     double Lrow[NC][NC];
     double roe_l[ND + 2], roe_r[ND + 2];
+    int rmode = 0;  // 2: every field linear on the wave; 1: all but the entropy field
 
     if (valid) {
         // cotangent of the face flux (local order)
@@ -205,39 +343,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
             for (int kk = 1; kk < ND; ++kk) nu[1 + kk] = fmad(R.ut[kk - 1], mul[NC - 1], mul[1 + kk]);
         }
-        // Stencil cell j of the face (0 .. 5 = i-2 .. i+3): the reconstruction
-        // of f+ holds it as value j (j <= 4), that of f- as value 5 - j
-        // (j >= 1).  a_s, b_s are the cotangents of those projected values.
-        // Read phase: the cotangent of the left eigenvector entries,
-        // sum over j of f+_j a_s + f-_j b_s (the split-flux cotangents L^T a
-        // and L^T b are added to the cells in the accumulation phase below).
-        double Lb[NC][NC];  // cotangent of the left eigenvector entries
-#pragma unroll
-        for (int s = 0; s < NC; ++s)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Lb[s][c] = 0.0;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
-            double a[NC], b[NC];
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
-                a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
-                b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
-            }
-            const double* fpj = ext + o + j;
-            const double* fmj = ext + (size_t)NC * cap + o + j;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double fp = fpj[(size_t)c * cap], fm = fmj[(size_t)c * cap];
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-                    if (!shear || c == 0) Lb[s][c] = fmad(fp, a[s], fmad(fm, b[s], Lb[s][c]));
-                }
-            }
-        }
+        // the reverse sums over the stencil, specialized on the fields whose
+        // reconstruction is linear on the whole wave (a wave-uniform choice)
+        constexpr uint32_t kAllKept = (1u << (6 * NC)) - 1u;
+        rmode = __all(masks == kAllKept) ? 2 : __all((masks | (63u << 6)) == kAllKept) ? 1 : 0;
+        double Lb[NC][NC];
+        if (rmode == 2)
+            rev_read<ND, (1 << NC) - 1>(ext, cap, o, masks, nu, ctab, Lb);
+        else if (rmode == 1)
+            rev_read<ND, ((1 << NC) - 1) & ~2>(ext, cap, o, masks, nu, ctab, Lb);
+        else
+            rev_read<ND, 0>(ext, cap, o, masks, nu, ctab, Lb);
 
         // left eigenvector entries -> Roe scalars
         {
@@ -312,44 +428,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // holding the read phase's values in registers
     __asm__ __volatile__("" ::: "memory");
     if (valid) {
-        // Accumulation phase: L^T a and L^T b added to the stencil cells as
-        // F-bar = (f+bar + f-bar)/2 and U-bar = alpha (f+bar - f-bar)/2.
-        // Lanes hold distinct cells at each j, and a wave's LDS operations
-        // complete in order, so the sums need no atomics.
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
-            double a[NC], b[NC];
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
-                a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
-                b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
-            }
-            double* cf = acc + o + j;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                double pb = 0.0, mb = 0.0;
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-                    if (!shear) {
-                        pb = fmad(Lrow[s][c], a[s], pb);
-                        mb = fmad(Lrow[s][c], b[s], mb);
-                    } else if (c == 0) {
-                        pb = fmad(Lrow[s][0], a[s], pb);
-                        mb = fmad(Lrow[s][0], b[s], mb);
-                    } else if (c == s) {
-                        pb += a[s];
-                        mb += b[s];
-                    }
-                }
-                cf[(size_t)c * cap] = fmad(0.5, pb + mb, cf[(size_t)c * cap]);
-                cf[(size_t)(NC + c) * cap] =
-                    fmad(0.5 * alpha, pb - mb, cf[(size_t)(NC + c) * cap]);
-            }
-            __asm__ __volatile__("" ::: "memory");
-        }
+        if (rmode == 2)
+            rev_acc<ND, (1 << NC) - 1>(acc, cap, o, masks, nu, Lrow, ctab, alpha);
+        else if (rmode == 1)
+            rev_acc<ND, ((1 << NC) - 1) & ~2>(acc, cap, o, masks, nu, Lrow, ctab, alpha);
+        else
+            rev_acc<ND, 0>(acc, cap, o, masks, nu, Lrow, ctab, alpha);
         // Roe cotangents of the face's two cells
         double* cr = acc + (size_t)(2 * NC) * cap + o;
 #pragma unroll
