@@ -278,9 +278,9 @@ int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes for teno_rhs_adjoint / teno_step_adjoint: six state-sized
- * buffers and the per-chunk partial gradients of the largest sweep (ncomp x
- * 74 doubles per 64 faces when the line has 63 cells or more, about 1.16
- * states).  0 for an invalid grid. */
+ * buffers and the per-chunk partial gradients of every axis (ncomp x 74
+ * doubles per 64 faces when the line has 63 cells or more, about 1.16 states
+ * per axis), which one gather pass sums.  0 for an invalid grid. */
 size_t teno_adjoint_workspace_bytes(const teno_grid* g);
 
 /* gradU_dev = A(U)^T lambda_dev with the LF speeds alpha_dev (3 device

@@ -20,10 +20,11 @@
 // of the Roe average (linear in mu_f), which are summed per staged cell in
 // LDS in a fixed order.  One lane per staged cell then applies the cell's
 // own Jacobian (fluxes, primitives, sqrt(rho), H) once and writes the chunk's
-// partial gradient of that cell.  Pass B (k_adj_gather, one thread per cell)
-// adds the partials of the at most two chunks that touch each image of the
-// cell (the cell itself and the ghost cells it supplies), in a fixed order,
-// so the result is deterministic without floating-point atomics.
+// partial gradient of that cell.  Pass B (k_adj_gather, one thread per cell,
+// once for all axes) adds the partials of the at most two chunks that touch
+// each image of the cell along each axis (the cell itself and the ghost
+// cells it supplies), in a fixed order, so the result is deterministic
+// without floating-point atomics.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -76,58 +77,101 @@ __device__ __forceinline__ constexpr double lin_coef(int m) {
 // frozen-weight reconstruction.  LM (compile time): the fields whose masks
 // are 7 for both signs on every face of the wave; their reconstruction is the
 // linear one for all of them, so their part of the sums factors through one
-// linear reconstruction per component (rev_read) and through
+// linear reconstruction per component (rev_read_fold) and through
 // g = sum_s L[s, :] nu_s (rev_acc).
-template <int ND, int LM>
-__device__ __forceinline__ void rev_read(const double* __restrict__ ext, int cap, int o,
-                                         uint32_t masks, const double (&nu)[ND + 2],
-                                         const double* __restrict__ ctab,
-                                         double (&Lb)[ND + 2][ND + 2]) {
+
+// Folds the cotangent x = Lb[s, :] of row s of the left eigenvector matrix
+// into the cotangents of the Roe scalars it is built from (rows of
+// left_row: acoustic 0.5 (b2 +- un ci, -b1 un -+ ci, -b1 ut, b1), entropy
+// (1 - b2, b1 un, b1 ut, -b1), shear (-ut, unit)).  Linear in x, so the rows
+// can be folded one at a time.
+template <int ND>
+__device__ __forceinline__ void fold_row(int s, const double* x, const FaceRoe<ND>& R,
+                                         double& un_b, double& ci_b, double& b1_b,
+                                         double& b2_b, double* ut_b) {
     constexpr int NC = ND + 2;
-    // Lb[s][c] = sum_j f+_j[c] a_s + f-_j[c] b_s: the cotangent of the left
-    // eigenvector entries
-    double h[NC];  // linear reconstruction of f+ and f- per component
+    if (s == 0 || s == NC - 1) {
+        const double sg = (s == 0) ? 0.5 : -0.5;
+        b2_b = fmad(0.5, x[0], b2_b);
+        un_b = fmad(sg * R.ci, x[0], fmad(-0.5 * R.b1, x[1], un_b));
+        ci_b = fmad(sg * R.un, x[0], fmad(-sg, x[1], ci_b));
+        b1_b = fmad(-0.5 * R.un, x[1], fmad(0.5, x[NC - 1], b1_b));
 #pragma unroll
-    for (int s = 0; s < NC; ++s)
+        for (int kk = 1; kk < ND; ++kk) {
+            b1_b = fmad(-0.5 * R.ut[kk - 1], x[1 + kk], b1_b);
+            ut_b[kk - 1] = fmad(-0.5 * R.b1, x[1 + kk], ut_b[kk - 1]);
+        }
+    } else if (s == 1) {
+        b2_b -= x[0];
+        un_b = fmad(R.b1, x[1], un_b);
+        b1_b = fmad(R.un, x[1], b1_b - x[NC - 1]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Lb[s][c] = 0.0;
+        for (int kk = 1; kk < ND; ++kk) {
+            b1_b = fmad(R.ut[kk - 1], x[1 + kk], b1_b);
+            ut_b[kk - 1] = fmad(R.b1, x[1 + kk], ut_b[kk - 1]);
+        }
+    } else if (s >= 2) {
+        ut_b[s - 2] -= x[0];
+    }
+}
+
+// Read phase of the reverse sums: Lb[s, c] = sum_j f+_j[c] a_s + f-_j[c] b_s
+// (the cotangent of the left eigenvector entries), folded row by row into
+// the Roe-scalar cotangents.  Linear fields: one linear reconstruction h of
+// f+ and f- per component, Lb[s, :] = nu_s h.  The others one field at a
+// time, re-reading the stencil, so that no more than one row is live.
+template <int ND, int LM>
+__device__ __forceinline__ void rev_read_fold(const double* __restrict__ ext, int cap, int o,
+                                              uint32_t masks, const double (&nu)[ND + 2],
+                                              const double* __restrict__ ctab,
+                                              const FaceRoe<ND>& R, double& un_b, double& ci_b,
+                                              double& b1_b, double& b2_b, double* ut_b) {
+    constexpr int NC = ND + 2;
+    const double* fp0 = ext + o;
+    const double* fm0 = ext + (size_t)NC * cap + o;
+    if (LM != 0) {
+        double h[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) h[c] = 0.0;
+        for (int c = 0; c < NC; ++c) h[c] = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const int jp = j <= 4 ? j : 4, jm = j >= 1 ? 5 - j : 0;
-        double a[NC], b[NC];
+        for (int j = 0; j < 6; ++j) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (j <= 4) h[c] = fmad(lin_coef(j), fp0[(size_t)c * cap + j], h[c]);
+                if (j >= 1) h[c] = fmad(lin_coef(5 - j), fm0[(size_t)c * cap + j], h[c]);
+            }
+        }
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            if (LM & (1 << s)) continue;
-            const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
-            a[s] = (j <= 4) ? nu[s] * ctab[mp * 5 + jp] : 0.0;
-            b[s] = (j >= 1) ? nu[s] * ctab[mm * 5 + jm] : 0.0;
-        }
-        const double* fpj = ext + o + j;
-        const double* fmj = ext + (size_t)NC * cap + o + j;
+            if (!(LM & (1 << s))) continue;
+            double x[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double fp = fpj[(size_t)c * cap], fm = fmj[(size_t)c * cap];
-            if (LM != 0) {
-                if (j <= 4) h[c] = fmad(lin_coef(jp), fp, h[c]);
-                if (j >= 1) h[c] = fmad(lin_coef(jm), fm, h[c]);
-            }
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                if (LM & (1 << s)) continue;
-                const bool shear = !(s == 0 || s == NC - 1) && s != 1;
-                if (!shear || c == 0) Lb[s][c] = fmad(fp, a[s], fmad(fm, b[s], Lb[s][c]));
-            }
+            for (int c = 0; c < NC; ++c) x[c] = nu[s] * h[c];
+            fold_row<ND>(s, x, R, un_b, ci_b, b1_b, b2_b, ut_b);
         }
     }
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-        if (!(LM & (1 << s))) continue;
+        if (LM & (1 << s)) continue;
+        // each field reads the stencil afresh (the compiler would otherwise
+        // hold all of it in registers across the fields)
+        __asm__ __volatile__("" ::: "memory");
         const bool shear = !(s == 0 || s == NC - 1) && s != 1;
+        const uint32_t mp = (masks >> (6 * s)) & 7u, mm = (masks >> (6 * s + 3)) & 7u;
+        double x[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (!shear || c == 0) Lb[s][c] = nu[s] * h[c];
+        for (int c = 0; c < NC; ++c) x[c] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double a = (j <= 4) ? nu[s] * ctab[mp * 5 + (j <= 4 ? j : 4)] : 0.0;
+            const double b = (j >= 1) ? nu[s] * ctab[mm * 5 + (j >= 1 ? 5 - j : 0)] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (shear && c != 0) continue;
+                x[c] = fmad(fp0[(size_t)c * cap + j], a, fmad(fm0[(size_t)c * cap + j], b, x[c]));
+            }
+        }
+        fold_row<ND>(s, x, R, un_b, ci_b, b1_b, b2_b, ut_b);
     }
 }
 
@@ -199,17 +243,15 @@ struct AdjArgs {
     const double* U;
     const double* lam;
     const double* alpha;  // 3 device doubles
-    double* P;            // chunk partials [chunk k][NC][cap][ncols]
-    double* out;
+    double* P;            // chunk partials of the axis [chunk k][NC][cap][ncols]
     AdjGeom G;            // geometry of the axis (teno_index.hpp)
-    int32_t accumulate;
     double dx;
     SchemeParams sch;
     DecisionConsts dk;
 };
 
 template <int ND, int DIR, bool A5>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_chunk(AdjArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_adj_chunk(AdjArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
@@ -347,30 +389,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         // reconstruction is linear on the whole wave (a wave-uniform choice)
         constexpr uint32_t kAllKept = (1u << (6 * NC)) - 1u;
         rmode = __all(masks == kAllKept) ? 2 : __all((masks | (63u << 6)) == kAllKept) ? 1 : 0;
-        double Lb[NC][NC];
         if (rmode == 2)
-            rev_read<ND, (1 << NC) - 1>(ext, cap, o, masks, nu, ctab, Lb);
+            rev_read_fold<ND, (1 << NC) - 1>(ext, cap, o, masks, nu, ctab, R, un_b, ci_b, b1_b,
+                                             b2_b, ut_b);
         else if (rmode == 1)
-            rev_read<ND, ((1 << NC) - 1) & ~2>(ext, cap, o, masks, nu, ctab, Lb);
+            rev_read_fold<ND, ((1 << NC) - 1) & ~2>(ext, cap, o, masks, nu, ctab, R, un_b, ci_b,
+                                                    b1_b, b2_b, ut_b);
         else
-            rev_read<ND, 0>(ext, cap, o, masks, nu, ctab, Lb);
-
-        // left eigenvector entries -> Roe scalars
-        {
-            const double a00 = Lb[0][0], a01 = Lb[0][1], l00 = Lb[NC - 1][0], l01 = Lb[NC - 1][1];
-            const double dA = 0.5 * (a00 - l00), sA = 0.5 * (a01 + l01);
-            b2_b += fmad(0.5, a00 + l00, -Lb[1][0]);
-            un_b = fmad(R.ci, dA, fmad(R.b1, Lb[1][1] - sA, un_b));
-            ci_b = fmad(R.un, dA, ci_b + 0.5 * (l01 - a01));
-            b1_b = fmad(R.un, Lb[1][1] - sA,
-                        b1_b + fmad(0.5, Lb[0][NC - 1] + Lb[NC - 1][NC - 1], -Lb[1][NC - 1]));
-#pragma unroll
-            for (int kk = 1; kk < ND; ++kk) {
-                const double t = fmad(-0.5, Lb[0][1 + kk] + Lb[NC - 1][1 + kk], Lb[1][1 + kk]);
-                b1_b = fmad(R.ut[kk - 1], t, b1_b);
-                ut_b[kk - 1] += fmad(R.b1, t, -Lb[1 + kk][0]);
-            }
-        }
+            rev_read_fold<ND, 0>(ext, cap, o, masks, nu, ctab, R, un_b, ci_b, b1_b, b2_b, ut_b);
         // derived scalars: b2 = b1 q2 / 2, b1 = gm1 / c2, ci = 1 / cs, cs = sqrt(c2),
         // c2 = gm1 (Hb - q2 / 2), q2 = |ub|^2
         q2_b = fmad(0.5 * R.b1, b2_b, q2_b);
@@ -527,38 +553,49 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-// Pass B: every cell adds the chunk partials of its images along DIR.
-template <int ND, int DIR>
-__global__ __launch_bounds__(256) void k_adj_gather(AdjArgs A) {
+// Pass B, once for all axes: every cell adds, axis by axis, the chunk
+// partials of its images along that axis (the cell itself and the ghost cells
+// it supplies), and writes the sum over the axes in the order x, y, z.
+struct GatherArgs {
+    const double* P[3];  // chunk partials of each axis
+    double* out;
+    AdjGeom G[3];        // geometry of each axis
+};
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_adj_gather(GatherArgs A) {
     constexpr int NC = ND + 2;
-    const AdjGeom& G = A.G;
     const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (cell >= G.ncell) return;
-    int64_t col, b;  // column and line of the cell along DIR
-    int i;           // its position on the line
-    adj_cell_place(G, DIR, cell, &col, &b, &i);
-    // images of the cell on its line: itself and the ghost cells it supplies
-    int img[7];
-    const int nimg = adj_images(G.bc, G.n, i, img);
-    double acc[NC];
+    if (cell >= A.G[0].ncell) return;
+    double tot[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int t = 0; t < nimg; ++t) {
-        // staged cell e = image + 3 of line b is in the stencils of faces e-5 .. e
-        const int e = img[t] + 3;
-        int64_t ka, kz;
-        adj_chunks_of(G, b, e, &ka, &kz);
-        for (int64_t kk = ka; kk <= kz; ++kk) {
-            const int slot = (int)adj_slot(G, b, e, kk);
+    for (int d = 0; d < ND; ++d) {
+        const AdjGeom& G = A.G[d];
+        const double* P = A.P[d];
+        int64_t col, b;  // column and line of the cell along d
+        int i;           // its position on the line
+        adj_cell_place(G, d, cell, &col, &b, &i);
+        int img[7];
+        const int nimg = adj_images(G.bc, G.n, i, img);
+        double acc[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += A.P[adj_p_index(G, NC, kk, c, slot, col)];
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        for (int t = 0; t < nimg; ++t) {
+            // staged cell e = image + 3 of line b is in the stencils of faces e-5 .. e
+            const int e = img[t] + 3;
+            int64_t ka, kz;
+            adj_chunks_of(G, b, e, &ka, &kz);
+            for (int64_t kk = ka; kk <= kz; ++kk) {
+                const int slot = (int)adj_slot(G, b, e, kk);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += P[adj_p_index(G, NC, kk, c, slot, col)];
+            }
         }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) tot[c] = (d == 0) ? acc[c] : tot[c] + acc[c];
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double* o = A.out + c * G.ncell + cell;
-        *o = A.accumulate ? *o + acc[c] : acc[c];
-    }
+    for (int c = 0; c < NC; ++c) A.out[c * A.G[0].ncell + cell] = tot[c];
 }
 
 // Elementwise combinations of the RK3 transpose (dt read from the device).
@@ -579,14 +616,16 @@ __global__ void k_adj_combo(int which, int64_t n, const double* dtp, const doubl
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Bytes of the chunk partials of axis d, and of all axes (each axis keeps
+// its own, so that one gather sums them).
+static size_t adj_P_axis_bytes(const teno_grid* g, int d) {
+    const AdjGeom G = adj_geom(g->n, g->bc, d);
+    return (size_t)adj_p_elems(G, g->ndim + 2) * sizeof(double);
+}
 static size_t adj_P_bytes(const teno_grid* g) {
-    size_t mx = 0;
-    for (int d = 0; d < g->ndim; ++d) {
-        const AdjGeom G = adj_geom(g->n, g->bc, d);
-        const size_t b = (size_t)adj_p_elems(G, g->ndim + 2) * sizeof(double);
-        if (b > mx) mx = b;
-    }
-    return mx;
+    size_t sum = 0;
+    for (int d = 0; d < g->ndim; ++d) sum += adj_P_axis_bytes(g, d);
+    return sum;
 }
 
 static size_t adj_state_bytes(const teno_grid* g) {
@@ -606,24 +645,27 @@ static hipError_t launch_adj(AdjArgs A, hipStream_t st) {
         hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true>), dim3((unsigned)nblk), dim3(64), lds, st, A);
     else
         hipLaunchKernelGGL((k_adj_chunk<ND, DIR, false>), dim3((unsigned)nblk), dim3(64), lds, st, A);
-    hipLaunchKernelGGL((k_adj_gather<ND, DIR>), dim3((unsigned)((A.G.ncell + 255) / 256)), dim3(256),
-                       0, st, A);
     return hipGetLastError();
 }
 
 static hipError_t rhs_adjoint_impl(const teno_grid* g, const double* U, const double* alpha,
                                    const double* lam, double* out, double* P, hipStream_t st) {
+    GatherArgs GA;
+    memset(&GA, 0, sizeof(GA));
+    GA.out = out;
+    char* pd = (char*)P;
     for (int d = 0; d < g->ndim; ++d) {
         AdjArgs A;
         memset(&A, 0, sizeof(A));
         A.U = U;
         A.lam = lam;
         A.alpha = alpha;
-        A.P = P;
-        A.out = out;
+        A.P = (double*)pd;
         A.G = adj_geom(g->n, g->bc, d);
         A.dx = g->dx[d];
-        A.accumulate = d > 0;
+        GA.P[d] = A.P;
+        GA.G[d] = A.G;
+        pd += adj_P_axis_bytes(g, d);
         A.sch = scheme_of(g);
         A.dk = decision_consts(g, false);
         if (A.G.kchunks * A.G.ncols > (int64_t(1) << 31) - 64) return hipErrorInvalidValue;
@@ -638,7 +680,13 @@ static hipError_t rhs_adjoint_impl(const teno_grid* g, const double* U, const do
         }
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    const unsigned blocks = (unsigned)((GA.G[0].ncell + 255) / 256);
+    switch (g->ndim) {
+        case 1: hipLaunchKernelGGL(k_adj_gather<1>, dim3(blocks), dim3(256), 0, st, GA); break;
+        case 2: hipLaunchKernelGGL(k_adj_gather<2>, dim3(blocks), dim3(256), 0, st, GA); break;
+        default: hipLaunchKernelGGL(k_adj_gather<3>, dim3(blocks), dim3(256), 0, st, GA); break;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace teno
