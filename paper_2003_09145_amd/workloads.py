@@ -372,6 +372,23 @@ def entropy_wave(ndim: int, n: int, t: float = 0.0, amp: float = 0.2, **kw):
     return prob, _as_field(prob, U)
 
 
+def contact(ndim: int, n: Sequence, rho=(1.0, 0.3), vel=(0.4, -0.3, 0.2), p: float = 1.0,
+            bc="periodic", **kw):
+    """Oblique contact discontinuity in the unit box: density rho[0] where the
+    sum of the cell-centre coordinates is below ndim / 2, rho[1] elsewhere;
+    uniform velocity (the first ndim entries of vel) and pressure.  The jump
+    in U and in each directional flux is a multiple of the entropy
+    eigenvector (1, u, v, w, |u|^2 / 2), which is the same in every direction,
+    so only the entropy field sees it."""
+    prob = uniform_problem(ndim, list(n), [0.0] * ndim, [1.0] * ndim, bc, **kw)
+    grids = np.meshgrid(*[prob.centres(k) for k in reversed(range(ndim))], indexing="ij")
+    s = sum(reversed(grids))
+    r = np.where(s < 0.5 * ndim, rho[0], rho[1])
+    U = conserved(r, [np.full_like(r, vel[k]) for k in range(ndim)], np.full_like(r, p),
+                  prob.gamma)
+    return prob, _as_field(prob, U)
+
+
 def random_field(prob: Problem, seed: int = 4, jumps: int = 3, modes: int = 4,
                  amp: float = 0.3) -> np.ndarray:
     """Positive-density, positive-pressure field: a few random Fourier modes

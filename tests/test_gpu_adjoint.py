@@ -53,6 +53,10 @@ SMALL = {
     "2d_teno5a": lambda: (lambda p: (p, W.random_field(p, seed=25)))(
         W.uniform_problem(2, [7, 6], [0.0, 0.0], [1.0, 1.0], ["periodic", "transmissive"],
                           scheme="teno5a")),
+    # contacts: only the entropy field is cut, so every chunk runs either the
+    # all-linear or the all-but-entropy-linear reverse
+    "1d_contact": lambda: W.contact(1, [20]),
+    "2d_contact": lambda: W.contact(2, [9, 8]),
 }
 
 
@@ -84,6 +88,8 @@ def test_rhs_adjoint_full_jacobian(torch, B, orc, name):
     ("3d_random9x5x131_mixed", lambda: (lambda p: (p, W.random_field(p, seed=33)))(
         W.uniform_problem(3, [9, 5, 131], [0.0] * 3, [1.0] * 3,
                           ["reflective", "transmissive", "periodic"]))),
+    ("1d_contact300", lambda: W.contact(1, [300])),
+    ("3d_contact40x36x33", lambda: W.contact(3, [40, 36, 33])),
     ("2d_teno5a_130x67", lambda: (lambda p: (p, W.random_field(p, seed=34)))(
         W.uniform_problem(2, [130, 67], [0.0, 0.0], [1.0, 1.0], ["transmissive", "periodic"],
                           scheme="teno5a"))),

@@ -444,6 +444,36 @@ def test_free_stream(orc, nd, bc):
     assert np.all(orc.rhs(prob, U) == 0.0)
 
 
+@pytest.mark.parametrize("nd,n", [(1, [300]), (2, [40, 33]), (3, [16, 14, 12])])
+def test_contact_seen_only_by_entropy_field(orc, nd, n):
+    # An oblique contact: density jumps, velocity and pressure are uniform.
+    # The jumps of U and of every directional flux are then multiples of
+    # (1, u, v, w, |u|^2 / 2), the entropy eigenvector of every direction,
+    # which the other left eigenvectors annihilate (characteristic
+    # reconstruction with Roe eigenvectors, Sec. 4).  So (i) only the entropy
+    # field's stencils are ever cut (eq 2.14) and (ii) velocity and pressure
+    # stay at rest: the momentum and energy RHS are u_d and |u|^2 / 2 times
+    # the density RHS.  A wrong entry of an acoustic or shear left row, or of
+    # the entropy column of R, breaks them (checked with planted mistakes in a
+    # copy of the oracle); the entropy row and the shear columns of R are
+    # pinned by the hand values and the flux-Jacobian test above.
+    prob, U = W.contact(nd, n)
+    a, _ = orc.alpha(prob, U)
+    R, dmp = orc.rhs(prob, U, a, dump=True)
+    nc = nd + 2
+    mask = dmp.reshape(-1, 2 * nc) >> 5          # byte 2 s + sign: field s
+    ent = mask[:, 2:4]
+    other = np.concatenate([mask[:, :2], mask[:, 4:]], axis=1)
+    assert np.all(other == 7)
+    assert np.count_nonzero((ent != 7).any(axis=1)) >= 10
+    vel = [0.4, -0.3, 0.2][:nd]
+    for k in range(nd):
+        bound = 1e-13 * np.abs(R[1 + k]).max()
+        assert np.abs(R[1 + k] - vel[k] * R[0]).max() <= bound
+    ke = 0.5 * sum(v * v for v in vel)
+    assert np.abs(R[-1] - ke * R[0]).max() <= 1e-12 * np.abs(R[-1]).max()
+
+
 # --------------------------------------------------------------------------
 # P9: fifth-order convergence of the Euler solver (smooth entropy wave)
 # --------------------------------------------------------------------------
