@@ -227,14 +227,15 @@ __constant__ const double kOmega[8][3] = {
     {omega_of(6, 0), omega_of(6, 1), omega_of(6, 2)},
     {omega_of(7, 0), omega_of(7, 1), omega_of(7, 2)}};
 
-// Decision constants of one launch: LAD ladder thresholds on x = max_k
-// chi~_k.  For the literal mapping m(x) = B_l + floor(theta (B_u - B_l)),
-// theta = 1 / (1 + x / H) (every operation rounded to nearest), m(x) >= B_l + j
-// holds exactly for x <= xthr[j - 1]; the host finds each threshold by
-// bisection over the doubles of the literal formula.
-constexpr int kMaxThr = 8;
+// Decision constants of one launch.  The LAD ladder index m = B_l +
+// floor(theta (B_u - B_l)), theta = 1 / (1 + x / H) with x = max_k chi~_k
+// (eq 3.1-3.4), is formed from an approximate x and theta and trusted when
+// y = theta (B_u - B_l) lies farther than ymarg from an integer: the literal
+// chain of correctly rounded operations differs from it by a few ulp.
 struct DecisionConsts {
-    double xthr[kMaxThr];  // unused entries hold -1 (never satisfied)
+    double inv_h;          // 1 / H
+    double nthr_d;         // B_u - B_l
+    double ymarg;          // kDecisionMargin (B_u - B_l)
     double ct_hi;          // largest C_T the scheme can use (10^-B_l or C_T)
     double ct_lo;          // smallest C_T (10^-B_u or C_T)
     int32_t nthr;          // B_u - B_l
@@ -248,11 +249,10 @@ struct DecisionConsts {
     // largest cutoff ct_hi: all three stencils are kept, whatever the ladder
     // index.  Negative: no such bound (never satisfied).
     double smooth_t;
-    // host products of the margins below: ct_hi (1 + margin), ct_lo (1 -
-    // margin) and margin |xthr[j]| (kept out of the kernels' loops, where the
-    // compiler would re-form them for every characteristic field)
+    // host products of the margins below: ct_hi (1 + margin) and ct_lo (1 -
+    // margin) (kept out of the kernels' loops, where the compiler would
+    // re-form them for every characteristic field)
     double hi_fac, lo_fac;
-    double xmarg[kMaxThr];
 };
 
 // Relative margin inside which an approximate decision value is not trusted
@@ -416,19 +416,16 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
             sure = isfinite(sum) && (k0 || c0) && (k1 || c1) && (k2 || c2);
             mask = (k0 ? 1u : 0u) | (k1 ? 2u : 0u) | (k2 ? 4u : 0u);
             if (S.scheme == 0 && (K.need_m || !sure)) {
-                // ladder index from the thresholds of the literal mapping
-                double x = t0;
-                if (t1 > x) x = t1;
-                if (t2 > x) x = t2;
-                bool msure = isfinite(x);
-                uint32_t above = 0;
-#pragma unroll
-                for (int j = 0; j < kMaxThr; ++j) {
-                    const double T = K.xthr[j];
-                    above += (x <= T) ? 1u : 0u;
-                    msure = msure && (fabs(x - T) > K.xmarg[j]);
-                }
-                m = (uint32_t)S.Bl + above;
+                // ladder index from approximate x and theta.  A NaN t_k makes
+                // sum NaN, which already sends the lane to the literal
+                // formula; the clamp keeps the table index in range for any x.
+                const double x = fmax(fmax(t0, t1), t2);
+                const double y = rcp_nr(__builtin_fma(x, K.inv_h, 1.0)) * K.nthr_d;
+                const double fl = floor(y);
+                const double fr = y - fl;
+                const bool msure =
+                    K.nthr == 0 || (isfinite(x) && fr > K.ymarg && fr < 1.0 - K.ymarg);
+                m = (uint32_t)S.Bl + (uint32_t)(int)fmin(fmax(fl, 0.0), K.nthr_d);
                 if (!sure) {
                     const double ct = kLadder[m];
                     const double rs = rcp_nr(sum);

@@ -64,19 +64,7 @@ inline SchemeParams scheme_of(const teno_grid* g) {
     return s;
 }
 
-
-// The literal LAD ladder index of eq 3.1-3.2 evaluated on the host (IEEE
-// binary64, round to nearest): m(x) = B_l + floor(theta (B_u - B_l)),
-// theta = 1 / (1 + x / H).
-inline int lad_m_host(double x, double H, int Bl, int Bu) {
-    const double theta = 1.0 / (1.0 + x / H);
-    if (theta >= 0.0) return Bl + (int)floor(theta * (double)(Bu - Bl));
-    return Bl;
-}
-
-// m(x) is non-increasing in x >= 0 (every operation is monotone), so for each
-// j = 1 .. B_u - B_l the set {x : m(x) >= B_l + j} is [0, X_j]; X_j is found
-// by bisection over the bit patterns of the non-negative doubles.
+// The cutoff ladder of eq 3.3 on the host: kLadderHost[k] = 10^-k.
 inline const double kLadderHost[21] = {1e0,   1e-1,  1e-2,  1e-3,  1e-4,  1e-5,  1e-6,
                                        1e-7,  1e-8,  1e-9,  1e-10, 1e-11, 1e-12, 1e-13,
                                        1e-14, 1e-15, 1e-16, 1e-17, 1e-18, 1e-19, 1e-20};
@@ -100,7 +88,7 @@ inline DecisionConsts decision_consts(const teno_grid* g, bool need_m) {
     DecisionConsts K = decision_consts_base(g, need_m);
     K.hi_fac = K.ct_hi * (1.0 + kDecisionMargin);
     K.lo_fac = K.ct_lo * (1.0 - kDecisionMargin);
-    for (int j = 0; j < kMaxThr; ++j) K.xmarg[j] = kDecisionMargin * std::fabs(K.xthr[j]);
+    K.ymarg = kDecisionMargin * K.nthr_d;
     return K;
 }
 
@@ -109,7 +97,6 @@ inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m) {
     memset(&K, 0, sizeof(K));
     K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
     K.need_m = need_m ? 1 : 0;
-    for (int j = 0; j < kMaxThr; ++j) K.xthr[j] = -1.0;
     K.smooth_t = -1.0;
     if (g->scheme == TENO_SCHEME_FIXED_CT) {
         K.ct_hi = K.ct_lo = g->ct_fixed;
@@ -130,23 +117,8 @@ inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m) {
     K.ct_lo = kLadderHost[g->Bu];
     K.smooth_t = smooth_bound(K.ct_hi);
     K.nthr = g->Bu - g->Bl;
-    if (K.nthr > kMaxThr) {  // more rungs than the fast path holds: literal decisions
-        K.literal = 1;
-        return K;
-    }
-    for (int j = 1; j <= K.nthr; ++j) {
-        uint64_t lo = 0, hi = 0x7ff0000000000000ull;  // m(0) = B_u, m(inf) = B_l
-        while (hi - lo > 1) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            double x;
-            memcpy(&x, &mid, sizeof(x));
-            if (lad_m_host(x, g->H, g->Bl, g->Bu) >= g->Bl + j)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        memcpy(&K.xthr[j - 1], &lo, sizeof(double));
-    }
+    K.nthr_d = (double)K.nthr;
+    K.inv_h = 1.0 / g->H;
     return K;
 }
 
