@@ -250,14 +250,17 @@ struct AdjArgs {
     DecisionConsts dk;
 };
 
-template <int ND, int DIR, bool A5>
+// CAPC: the LDS row stride when it is known at compile time (ext_cap_for(n)
+// = 74 for every n >= 63), so that every row of a staged cell is an immediate
+// offset from one address; 0: taken from the geometry.
+template <int ND, int DIR, bool A5, int CAPC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_adj_chunk(AdjArgs A) {
     constexpr int NC = ND + 2;
     constexpr int NV = 2 * NC + ND + 2;  // f+ (NC), f- (NC), sqrt(rho), u (ND), H
     using LO = LocalOrder<ND, DIR>;
     extern __shared__ double smem[];
     const AdjGeom& G = A.G;
-    const int cap = G.cap;
+    const int cap = CAPC ? CAPC : G.cap;
     double* omega = smem;       // 24: eq 2.15 weights per cutoff mask
     double* ctab = smem + 24;   // 40: cand_coef per (mask, stencil value)
     double* ext = smem + 64;    // NV x cap staged rows (forward quantities)
@@ -641,10 +644,20 @@ static hipError_t launch_adj(AdjArgs A, hipStream_t st) {
     constexpr int NV = 2 * (ND + 2) + ND + 2;
     const int64_t nblk = A.G.kchunks * A.G.ncols;
     const size_t lds = (size_t)(64 + NV * A.G.cap) * sizeof(double);
-    if (A.sch.scheme == TENO_SCHEME_TENO5A)
-        hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true>), dim3((unsigned)nblk), dim3(64), lds, st, A);
-    else
-        hipLaunchKernelGGL((k_adj_chunk<ND, DIR, false>), dim3((unsigned)nblk), dim3(64), lds, st, A);
+    constexpr int kCapLong = 74;  // ext_cap_for(n) for every n >= 63
+    const bool a5 = A.sch.scheme == TENO_SCHEME_TENO5A;
+    if (A.G.cap == kCapLong) {
+        if (a5)
+            hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true, kCapLong>), dim3((unsigned)nblk),
+                               dim3(64), lds, st, A);
+        else
+            hipLaunchKernelGGL((k_adj_chunk<ND, DIR, false, kCapLong>), dim3((unsigned)nblk),
+                               dim3(64), lds, st, A);
+    } else if (a5) {
+        hipLaunchKernelGGL((k_adj_chunk<ND, DIR, true, 0>), dim3((unsigned)nblk), dim3(64), lds, st, A);
+    } else {
+        hipLaunchKernelGGL((k_adj_chunk<ND, DIR, false, 0>), dim3((unsigned)nblk), dim3(64), lds, st, A);
+    }
     return hipGetLastError();
 }
 
