@@ -1005,7 +1005,7 @@ def summarize_adjoint_trace(d, log=None):
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/adj -o adj -- "
         "python3 bench.py --adjoint-3d-only",
         "#   python3 bench.py --summarize-adjoint-trace $OUT [its JSON line]",
-        "# k_adj_chunk: pass A per axis; k_adj_gather: pass B per axis; k_sweep: the",
+        "# k_adj_chunk: pass A per axis; k_adj_gather: pass B, once for all axes; k_sweep: the",
         "# forward sweeps of teno_rhs",
         f"source_sha256: {sources_sha()}",
         "#",
