@@ -35,6 +35,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-extras]
        python bench.py --copy-calibration          (plain 1 GiB copies)
        python bench.py --summarize-counters DIR    (rocprofv3 CSV -> profiles/)
+       python bench.py --summarize-clock DIR       (GRBM clock counters -> profiles/)
 Prints one JSON line (the benchmark modes).
 """
 from __future__ import annotations
@@ -56,6 +57,11 @@ PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 METRIC = "TENO RHS cell-updates/s (256³ FP64), % HBM roofline; batched/adjoint vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_3d_256_traffic.txt")
+CLOCK_FILE = os.path.join(ROOT, "profiles", "k_sweep_3d_256_clock.txt")
+# MI355X: 8 XCDs, whose GRBM_GUI_ACTIVE counts (GPU clock cycles while busy)
+# rocprofv3 sums per dispatch; the clock the published FP64 peak assumes
+N_XCD = 8
+PEAK_CLOCK_GHZ = 2.4
 SWEEP_SOURCES = ["paper_2003_09145_amd/csrc/teno_kernels.hip",
                  "paper_2003_09145_amd/csrc/teno_face.hpp",
                  "paper_2003_09145_amd/csrc/teno_device.hpp",
@@ -147,13 +153,13 @@ def match_kernel(names, kernel: str):
     return [k for k in names if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
 
 
-def _load_counter_rows(prefix: str, kernel: str):
-    """The key=value fields of the committed counter summary's `prefix` line
+def _load_counter_rows(prefix: str, kernel: str, path: str = TRAFFIC_FILE):
+    """The key=value fields of a committed counter summary's `prefix` line
     for `kernel`, or None when the sweep sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     sha, vals = None, {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("source_sha256:"):
             sha = line.split(":", 1)[1].strip()
         elif line.startswith(prefix + " "):
@@ -171,6 +177,13 @@ def load_traffic(kernel: str):
     summary, or None when the sweep sources changed since it was taken."""
     kv = _load_counter_rows("kernel", kernel)
     return None if kv is None else float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+
+
+def load_clock_ghz(kernel: str):
+    """Mean GPU clock during launches of `kernel` (GRBM_GUI_ACTIVE per XCD
+    over the dispatch duration) from the committed summary, or None."""
+    kv = _load_counter_rows("clock", kernel, CLOCK_FILE)
+    return None if kv is None else float(kv["clock_GHz"])
 
 
 def load_executed_flop(kernel: str):
@@ -234,6 +247,7 @@ def headline(args, B, W, torch):
     kname = f"k_sweep<3,{dom},{SWEEP_WAVES[dom]},false>"
     traffic = load_traffic(kname)
     executed = load_executed_flop(kname)
+    clock = load_clock_ghz(kname)
     alg_bytes = sweep_bytes(3, n3, dom, fused_rk=fused)
     roofline = {
         "bound": "alu",
@@ -260,6 +274,14 @@ def headline(args, B, W, torch):
         "fp64_counter_flop_per_launch": executed,
         "fp64_counter_frac": (None if executed is None else
                               round(executed / (per_axis[dom] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)),
+        # the GPU clock this kernel sustains (committed GRBM counter summary)
+        # and the FP64 peak scaled to it: the published peak assumes 2.4 GHz
+        "sustained_clock_GHz": clock,
+        "peak_at_sustained_clock": (None if clock is None else
+                                    round(PEAK_FP64_TFLOPS * clock / PEAK_CLOCK_GHZ, 1)),
+        "frac_at_sustained_clock": (None if clock is None else
+                                    round(achieved / (PEAK_FP64_TFLOPS * clock / PEAK_CLOCK_GHZ),
+                                          4)),
         "sweep_ms_xyz": [round(x, 4) for x in per_axis],
     }
     step_s = ms * 1e-3 / args.steps
@@ -811,6 +833,46 @@ def _short(name):
     return m.group(1) + (m.group(2) or "").replace(" ", "").replace("(int)", "")
 
 
+def summarize_clock(d):
+    """profiles/k_sweep_3d_256_clock.txt from a GRBM_GUI_ACTIVE run under
+    d/grbm: per kernel, the busy GPU cycles per dispatch, the dispatch
+    duration and their ratio per XCD, the clock the kernel ran at."""
+    per = {}
+    for p in glob.glob(os.path.join(d, "grbm", "**", "*counter_collection.csv"), recursive=True):
+        with open(p, newline="") as f:
+            for r in csv.DictReader(f):
+                key = {k.lower(): v for k, v in r.items()}
+                if key.get("counter_name") != "GRBM_GUI_ACTIVE":
+                    continue
+                dur = float(key["end_timestamp"]) - float(key["start_timestamp"])
+                per.setdefault(_short(key["kernel_name"]), []).append(
+                    (float(key["counter_value"]), dur))
+    lines = [
+        "# GPU clock during the 3D sweeps and the LF-speed reduction, 256^3 turbulence",
+        "#",
+        "# command (from the repository root, after cd /tmp && export TMPDIR=/tmp; $OUT is any",
+        "# output directory):",
+        "#   rocprofv3 --pmc GRBM_GUI_ACTIVE GRBM_COUNT --output-format csv -d $OUT/grbm -o g -- "
+        "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
+        "#   python3 bench.py --summarize-clock $OUT",
+        f"# clock_GHz = GRBM_GUI_ACTIVE / {N_XCD} XCDs / dispatch duration (rocprofv3 sums the",
+        "# counter over the XCDs); the published FP64 peak of 78.6 TFLOP/s assumes 2.4 GHz",
+        f"source_sha256: {sources_sha()}",
+        "#",
+    ]
+    for k in sorted(per):
+        if not (k.startswith("k_sweep<3") or k.startswith("k_alpha<3")):
+            continue
+        v = per[k]
+        cyc = sum(a for a, _ in v) / len(v)
+        dur = sum(b for _, b in v) / len(v)
+        lines.append(f"clock {k}: grbm_gui_active={cyc:.0f}, duration_ns={dur:.0f}, "
+                     f"clock_GHz={cyc / N_XCD / dur:.3f}, dispatches={len(v)}")
+    with open(CLOCK_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_counters(d):
     fetch = _read_counters(os.path.join(d, "fetch"))
     write = _read_counters(os.path.join(d, "write"))
@@ -1049,11 +1111,15 @@ def main():
                     help="headline only (no schemes / batched / adjoint legs)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
+    ap.add_argument("--summarize-clock", metavar="DIR")
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DIR", "BENCH_JSON"))
     ap.add_argument("--adjoint-3d-only", action="store_true",
                     help="time teno_rhs and teno_rhs_adjoint on the 3D field only (profiling)")
     ap.add_argument("--summarize-adjoint-trace", nargs="+", metavar=("DIR", "JSON"))
     args = ap.parse_args()
+    if args.summarize_clock:
+        summarize_clock(args.summarize_clock)
+        return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
         return
