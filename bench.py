@@ -153,9 +153,11 @@ def match_kernel(names, kernel: str):
     return [k for k in names if k == kernel or k.startswith(kernel.rstrip(">") + ",")]
 
 
-def _load_counter_rows(prefix: str, kernel: str, path: str = TRAFFIC_FILE):
+def _load_counter_rows(prefix: str, kernel: str, path: str = None):
     """The key=value fields of a committed counter summary's `prefix` line
-    for `kernel`, or None when the sweep sources changed since it was taken."""
+    for `kernel` (the traffic summary unless `path` names another), or None
+    when the sweep sources changed since it was taken."""
+    path = TRAFFIC_FILE if path is None else path
     if not os.path.exists(path):
         return None
     sha, vals = None, {}
