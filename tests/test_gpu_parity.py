@@ -495,6 +495,23 @@ FULL_RUNS = {
 }
 
 
+@pytest.mark.parametrize("name,prob_u,nsteps", [
+    # the Shu-Osher problem of Sec. 4.2 to its final time
+    ("shu_osher400_t1.8", lambda: W.shu_osher(400), None),
+    # 3D periodic turbulence through 200 adaptive steps (t = 2.79)
+    ("turbulence_3d_24_200steps", lambda: W.turbulence_3d(24), 200),
+])
+def test_long_run(torch, B, orc, name, prob_u, nsteps):
+    prob, U = prob_u()
+    t_end = 1.8 if nsteps is None else np.inf
+    Uc, t, k = orc.run(prob, U, 0.5, t_end=t_end, nsteps=nsteps)
+    Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9 if nsteps else t_end, k if nsteps else k + 5)
+    print(f"[long run] {name}: {k} steps to t = {t}, device {c.nsteps} steps to t = {c.t}, "
+          f"bitwise {np.array_equal(Ug, Uc)}", flush=True)
+    assert c.status == 0 and c.nsteps == k and c.t == t
+    assert np.array_equal(Ug, Uc)
+
+
 @pytest.mark.parametrize("name", list(FULL_RUNS))
 def test_full_run_to_final_time(torch, B, orc, name):
     mk, t_end = FULL_RUNS[name]
