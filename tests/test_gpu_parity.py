@@ -487,6 +487,12 @@ def test_boundary_parity(torch, B, orc, name, steps):
 FULL_RUNS = {
     "riemann_case1_128x128_t0.3": (lambda: W.riemann_2d_table2(1, 128), 0.3),
     "riemann_case2_128x128_t0.25": (lambda: W.riemann_2d_table2(2, 128), 0.25),
+    # the comparison schemes of Table 2 on case 1: TENO5 with the default
+    # C_T = 1e-7, TENO5-A with the adjusted alpha_2 = 5.5, C_r = 0.3
+    "riemann_case1_teno5_128x128_t0.3":
+        (lambda: W.riemann_2d_table2(1, 128, scheme="fixed_ct", ct_fixed=1e-7), 0.3),
+    "riemann_case1_teno5a_128x128_t0.3":
+        (lambda: W.riemann_2d_table2(1, 128, scheme="teno5a", a2=5.5, cr=0.3), 0.3),
     "rayleigh_taylor_32x128_t1.95": (lambda: W.rayleigh_taylor(32, 128), 1.95),
     # the double Mach reflection with H = 1: with the printed H = 10 the
     # method goes non-physical in a wall cell ahead of the shock foot
