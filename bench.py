@@ -441,10 +441,13 @@ def table2_leg(args, B, W, torch):
             row["speedup_vs_paper_present"] = round(paper[3] * 1e3 / row["lad"]["ms_per_step"], 1)
         if t_final_of(case) is not None and grid_s in ("128x512", "1024x1024", "1024x256"):
             # TENO5-LAD with the paper's parameters to the paper's final time
-            # (the double Mach reflection also with H = 1, see the notes)
+            # (the double Mach reflection also with H = 1, and with H = 10
+            # under the cut form of the eq 3.2 sensor: theta = 0 where max
+            # chi-tilde > H)
             runs = {"lad_full_run": {}}
             if case.startswith("Double"):
                 runs["lad_H1_full_run"] = {"H": 1.0}
+                runs["lad_cut_full_run"] = {"theta": "cut"}
             for key, kw in runs.items():
                 S = B.Solver(prob0.replace(**kw))
                 Ud = Ud0.clone()

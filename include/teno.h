@@ -112,7 +112,8 @@ typedef struct teno_grid {
                           0 <= Bl <= Bu <= 20                                   */
     double eps;        /* epsilon of eq 2.8 and eq 3.2 (paper: 1e-6)            */
     int32_t flags;     /* TENO_FLAG_* (0 for normal use)                        */
-    int32_t reserved_;
+    int32_t theta;     /* LAD theta form of eq 3.2: TENO_THETA_PRINTED (0) or
+                          TENO_THETA_CUT (1); other schemes ignore it          */
     double a1, a2;     /* TENO5-A alpha_1, alpha_2 of eq 2.16 (paper: 10.5, 3.5);
                           0 <= a1 - a2, a1 <= 20                                */
     double cr;         /* TENO5-A C_r of eq 2.17 (paper: 0.25); 0 < 0.9 cr < 1  */
@@ -131,6 +132,17 @@ typedef struct teno_grid {
  * cutoff-mask digest into ctrl.digest while ctrl.want_digest is set.  Without
  * this flag the sweeps carry no digest code and ctrl.digest is left alone. */
 #define TENO_FLAG_MASK_DIGEST 2
+
+/* teno_grid.theta: the LAD sensor of eq 3.2, with x = max_k chi-tilde_k.
+ * TENO_THETA_PRINTED: theta = 1 / (1 + x / H) as printed.
+ * TENO_THETA_CUT: theta = 0 where x > H, the printed form elsewhere.  Sec. 3
+ * describes H as the threshold above which the whole stencil counts as
+ * discontinuous, and theta = 0 as the value of a discontinuity (C_T =
+ * 10^-B_l); the printed form gives theta = 1/2 at x = H instead.  With H = 10
+ * the cut form runs the double Mach reflection of Sec. 4.3.3 to t = 0.2,
+ * which the printed form does not. */
+#define TENO_THETA_PRINTED 0
+#define TENO_THETA_CUT 1
 
 /* Time-stepping control block.  Lives in DEVICE memory so that step loops
  * never synchronise with the host and can be captured in a HIP graph. */

@@ -32,6 +32,9 @@ _LIB_LITERAL = os.path.join(_HERE, "liboracle_literal.so")
 
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
+# LAD theta of eq 3.2: as printed, or also 0 where max chi-tilde > H (Sec. 3's
+# description of H)
+THETA = {"printed": 0, "cut": 1}
 
 
 class OrParams(ctypes.Structure):
@@ -58,6 +61,7 @@ class OrParams(ctypes.Structure):
         ("side_state", ctypes.c_double * 60),
         ("gravity", ctypes.c_double * 3),
         ("time", ctypes.c_double),
+        ("theta_form", ctypes.c_int32),
     ]
 
 
@@ -154,6 +158,8 @@ def params(prob) -> OrParams:
     p.a2 = float(_get(prob, "a2", 3.5))
     p.cr = float(_get(prob, "cr", 0.25))
     p.xi = float(_get(prob, "xi", 1e-3))
+    tf = _get(prob, "theta", "printed")
+    p.theta_form = THETA[tf] if isinstance(tf, str) else int(tf)
     bnd = _get(prob, "boundary", None)
     if bnd is not None:
         kinds = dict(BC, fixed=3)

@@ -37,6 +37,10 @@
  *    t + dt/2);
  *  - the gravity source of the Rayleigh-Taylor problem is added after the
  *    flux differences;
+ *  - the LAD sensor theta of eq 3.2 as printed, 1 / (1 + x / H) with x the
+ *    largest chi-tilde_k, or (theta_form 1) that form cut to 0 wherever
+ *    x > H: Sec. 3 calls such a stencil discontinuous and gives theta = 0
+ *    for a discontinuity, while the printed form is 1/2 at x = H;
  *  - rounding of the sums of products (the paper fixes none).  The file
  *    builds in two modes:
  *      default: the smoothness indicators (eq 2.9-2.11), candidate fluxes
@@ -87,6 +91,8 @@ typedef struct {
     double side_state[3][2][2][5]; /* conserved fixed states (natural order)        */
     double gravity[3];             /* momentum += rho g, energy += m . g            */
     double time;                   /* time of or_rhs evaluations                    */
+    int32_t theta_form;            /* LAD theta of eq 3.2: 0 as printed; 1 also
+                                      theta = 0 where max chi-tilde exceeds H      */
 } OrParams;
 
 }  // extern "C"
@@ -220,7 +226,13 @@ Decision teno_decide(const OrParams& P, double a, double b, double c, double d,
         x = t[0];
         if (t[1] > x) x = t[1];
         if (t[2] > x) x = t[2];
-        theta = 1.0 / (1.0 + x / P.H);
+        /* theta_form 1: Sec. 3 calls a stencil whose largest chi-tilde is over
+         * H discontinuous, and theta is 0 for a discontinuity; the printed
+         * form would give 1/2 at x = H, so this form sets theta = 0 there. */
+        if (P.theta_form == 1 && x > P.H)
+            theta = 0.0;
+        else
+            theta = 1.0 / (1.0 + x / P.H);
         /* A NaN theta only arises from a non-physical stencil (flagged by the
          * positivity status); it takes the most dissipative rung B_l. */
         if (theta >= 0.0)

@@ -20,6 +20,8 @@ OK, ERR_ARG, ERR_DEVICE, ERR_NONPHYSICAL = 0, 1, 2, 3
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 BC_FIXED = 3
 SCHEME = {"lad": 0, "fixed_ct": 1, "linear5": 2, "teno5a": 3}
+# teno_grid.theta: the LAD sensor of eq 3.2 as printed, or cut to 0 above H
+THETA = {"printed": 0, "cut": 1}
 
 
 class TenoSide(ctypes.Structure):
@@ -54,7 +56,7 @@ class TenoGrid(ctypes.Structure):
         ("Bu", ctypes.c_int32),
         ("eps", ctypes.c_double),
         ("flags", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("theta", ctypes.c_int32),
         ("a1", ctypes.c_double),
         ("a2", ctypes.c_double),
         ("cr", ctypes.c_double),
@@ -210,6 +212,8 @@ def grid(prob) -> TenoGrid:
     g.a2 = float(_get(prob, "a2", 3.5))
     g.cr = float(_get(prob, "cr", 0.25))
     g.xi = float(_get(prob, "xi", 1e-3))
+    th = _get(prob, "theta", "printed")
+    g.theta = THETA[th] if isinstance(th, str) else int(th)
     g.flags = ((FLAG_LITERAL_DECISIONS if _get(prob, "literal_decisions", False) else 0) |
                (FLAG_MASK_DIGEST if _get(prob, "mask_digest", False) else 0))
     bnd = _get(prob, "boundary", None)

@@ -23,6 +23,7 @@ struct SchemeParams {
     int32_t scheme;  // 0 LAD, 1 fixed C_T, 2 linear (all stencils kept), 3 TENO5-A
     int32_t Bl, Bu;
     int32_t kA_nan;  // TENO5-A: exponent taken by a non-finite sensor, floor(a1 - a2)
+    int32_t theta_cut;  // LAD: 1 sets theta = 0 where max chi~ > H (eq 3.2, cut form)
     double bu_bl;    // LAD: (double)(B_u - B_l) (host-converted)
     double a1, a2;   // TENO5-A: alpha_1, alpha_2 of eq 2.16
     double cr;       // TENO5-A: C_r of eq 2.17
@@ -253,6 +254,10 @@ struct DecisionConsts {
     // margin) (kept out of the kernels' loops, where the compiler would
     // re-form them for every characteristic field)
     double hi_fac, lo_fac;
+    // cut form of theta: max chi~ above h_hi = H (1 + margin) is certainly over
+    // H (m = B_l), at or above h_lo = H (1 - margin) it is not trusted; NaN for
+    // the printed form, so that neither test holds
+    double h_hi, h_lo;
 };
 
 // Relative margin inside which an approximate decision value is not trusted
@@ -321,11 +326,15 @@ __device__ __forceinline__ uint32_t teno5_decide_literal(const SchemeParams& S, 
         double x = t0;
         if (t1 > x) x = t1;
         if (t2 > x) x = t2;
-        const double theta = cr_div(1.0, 1.0 + cr_div(x, S.H));
-        if (theta >= 0.0)
-            m = S.Bl + (int)floor(theta * S.bu_bl);
-        else
-            m = S.Bl;
+        if (S.theta_cut && x > S.H) {
+            m = S.Bl;  // theta = 0: the stencil counts as discontinuous
+        } else {
+            const double theta = cr_div(1.0, 1.0 + cr_div(x, S.H));
+            if (theta >= 0.0)
+                m = S.Bl + (int)floor(theta * S.bu_bl);
+            else
+                m = S.Bl;
+        }
         ct = kLadder[m];
     } else if (A5) {
         ct = teno5a_cutoff(S, a, b, c, d, e, &m);
@@ -423,9 +432,17 @@ __device__ __forceinline__ double teno5_rec_fast(const SchemeParams& S, const De
                 const double y = rcp_nr(__builtin_fma(x, K.inv_h, 1.0)) * K.nthr_d;
                 const double fl = floor(y);
                 const double fr = y - fl;
-                const bool msure =
+                bool msure =
                     K.nthr == 0 || (isfinite(x) && fr > K.ymarg && fr < 1.0 - K.ymarg);
                 m = (uint32_t)S.Bl + (uint32_t)(int)fmin(fmax(fl, 0.0), K.nthr_d);
+                // cut form of theta: x certainly over H gives B_l; x within
+                // the margin of H takes the literal formula
+                if (x > K.h_hi) {
+                    m = (uint32_t)S.Bl;
+                    msure = true;
+                } else if (x >= K.h_lo) {
+                    msure = false;
+                }
                 if (!sure) {
                     const double ct = kLadder[m];
                     const double rs = rcp_nr(sum);

@@ -39,6 +39,7 @@ inline int validate(const teno_grid* g) {
     }
     if (!(g->eps > 0.0)) return TENO_ERR_ARG;
     if (g->flags & ~(TENO_FLAG_LITERAL_DECISIONS | TENO_FLAG_MASK_DIGEST)) return TENO_ERR_ARG;
+    if (g->theta != TENO_THETA_PRINTED && g->theta != TENO_THETA_CUT) return TENO_ERR_ARG;
     return TENO_OK;
 }
 
@@ -56,6 +57,7 @@ inline SchemeParams scheme_of(const teno_grid* g) {
     s.a2 = g->a2;
     s.cr = g->cr;
     s.kA_nan = 0;
+    s.theta_cut = (g->scheme == TENO_SCHEME_LAD && g->theta == TENO_THETA_CUT) ? 1 : 0;
     s.epsA = 0.0;
     if (g->scheme == 3) {
         s.kA_nan = (int)std::floor(g->a1 - g->a2);
@@ -98,6 +100,7 @@ inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m) {
     K.literal = (g->flags & TENO_FLAG_LITERAL_DECISIONS) ? 1 : 0;
     K.need_m = need_m ? 1 : 0;
     K.smooth_t = -1.0;
+    K.h_hi = K.h_lo = NAN;
     if (g->scheme == TENO_SCHEME_FIXED_CT) {
         K.ct_hi = K.ct_lo = g->ct_fixed;
         K.smooth_t = smooth_bound(K.ct_hi);
@@ -119,6 +122,11 @@ inline DecisionConsts decision_consts_base(const teno_grid* g, bool need_m) {
     K.nthr = g->Bu - g->Bl;
     K.nthr_d = (double)K.nthr;
     K.inv_h = 1.0 / g->H;
+    if (g->theta == TENO_THETA_CUT) {
+        // the approximate max chi~ is within a few ulp of the literal one
+        K.h_hi = g->H * (1.0 + kDecisionMargin);
+        K.h_lo = g->H * (1.0 - kDecisionMargin);
+    }
     return K;
 }
 

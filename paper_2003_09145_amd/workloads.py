@@ -59,6 +59,7 @@ class Problem:
     H: float = 10.0              # LAD parameters (Sec. 4)
     Bl: int = 4
     Bu: int = 10
+    theta: str = "printed"       # LAD sensor of eq 3.2: "printed", or "cut" (0 above H)
     eps: float = 1e-6            # epsilon of eq 2.8 (Sec. 2)
     a1: float = 10.5             # TENO5-A parameters (eq 2.16-2.18, Sec. 4 defaults)
     a2: float = 3.5

@@ -211,6 +211,41 @@ def test_rhs_parity_other_schemes(torch, B, orc, scheme):
     assert flips == 0 and rel <= REL and bitwise
 
 
+# The cut form of the LAD sensor (theta = 0 where max chi-tilde > H, Sec. 3's
+# description of H): every decision (ladder index and mask) through the fast
+# path and through the literal formula, and steps without decision dumps.
+# (inputs with stencils whose max chi-tilde lies in (H, 5 H], where the two
+# forms give different ladder indices)
+@pytest.mark.parametrize("name,steps", [("1d_random131_reflective", 4),
+                                        ("2d_random67x45_mixed", 3),
+                                        ("3d_random21x18x13_mixed", 2),
+                                        ("3d_random64x65x70_mixed", 1)])
+def test_lad_cut_form_parity(torch, B, orc, name, steps):
+    prob, U = CASES[name]()
+    prob = prob.replace(theta="cut")
+    Rg, dg, _, _ = _gpu_rhs(torch, B, prob, U)
+    Rc, dc = orc.rhs(prob, U, dump=True)
+    flips, rel, bitwise = compare(Rg, Rc, dg, dc, name + " cut")
+    assert flips == 0 and bitwise
+    # the printed form differs on this input (some stencil has max chi~ > H)
+    _, dp, _, _ = _gpu_rhs(torch, B, prob.replace(theta="printed"), U)
+    m_cut, m_printed = dg & 31, dp & 31
+    print(f"[cut form] {name}: ladder indices that differ from the printed form: "
+          f"{int(np.count_nonzero(m_cut != m_printed))} of {dg.size}", flush=True)
+    assert np.count_nonzero(m_cut != m_printed) > 0
+    lit = prob.replace()
+    lit.literal_decisions = True
+    Rl, dl, _, _ = _gpu_rhs(torch, B, lit, U)
+    assert np.array_equal(Rl, Rg) and np.array_equal(dl, dg)
+    Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
+    Uc = U.copy()
+    t = 0.0
+    for _ in range(steps):
+        Uc, t, dt, a9, st = orc.step(prob, Uc, 0.5, t, 1e9)
+    assert c.status == st and c.t == t
+    assert np.array_equal(Ug, Uc)
+
+
 # TENO5-A (eq 2.16-2.18): RHS with every decision (cutoff exponent and
 # mask), the literal-decision mode, and steps (no decision dump, so the
 # smooth-stencil shortcut is on), with the default and the Rayleigh-Taylor
@@ -498,6 +533,9 @@ FULL_RUNS = {
     # method goes non-physical in a wall cell ahead of the shock foot
     "double_mach_H1_128x32_t0.2":
         (lambda: (lambda p, u: (p.replace(H=1.0), u))(*W.double_mach(128, 32)), 0.2),
+    # ... and with H = 10 under the cut form of the sensor (theta = 0 where
+    # max chi-tilde > H)
+    "double_mach_cut_128x32_t0.2": (lambda: W.double_mach(128, 32, theta="cut"), 0.2),
 }
 
 
@@ -529,6 +567,22 @@ def test_full_run_to_final_time(torch, B, orc, name):
           f"bitwise {np.array_equal(Ug, Uc)}", flush=True)
     assert c.status == 0 and c.nsteps == k and c.t == t == t_end
     assert np.array_equal(Ug, Uc)
+
+
+def test_double_mach_full_size_cut_form(torch, B):
+    # Sec. 4.3.3 at the Table 2 grid 1024 x 256 with H = 10 to t = 0.2: the
+    # printed sensor goes non-physical within the first steps, the cut form
+    # runs to the final time
+    t_end = 0.2
+    out = {}
+    for theta in ("printed", "cut"):
+        prob, U = W.double_mach(1024, 256, theta=theta)
+        Ug, c = _gpu_steps(torch, B, prob, U, 0.5, t_end, 5000)
+        out[theta] = (int(c.status), float(c.t), int(c.nsteps), float(Ug[0].min()))
+        print(f"[double Mach 1024x256 H=10] theta {theta}: status {c.status} t {c.t} "
+              f"steps {c.nsteps} rho_min {Ug[0].min():.4f}", flush=True)
+    assert out["printed"][0] == 3 and out["printed"][1] < 0.01
+    assert out["cut"][0] == 0 and out["cut"][1] == t_end and out["cut"][3] > 0.0
 
 
 def test_boundary_rejected_by_adjoint_and_batch(torch, B):

@@ -180,6 +180,55 @@ def test_lad_crafted_family(orc, x, m_exp, kept2):
     assert abs(f - (-0.3 * s / 6.0 if kept2 else 0.0)) < 1e-16
 
 
+CUT = {"ndim": 1, "n": [8], "dx": [1.0], "bc": "periodic", "theta": "cut"}
+
+
+@pytest.mark.parametrize("x,m_exp,kept2", [
+    (0.5, 9, True), (3.0, 8, True), (7.0, 7, True), (9.9, 7, True),
+    (10.5, 4, False), (15.0, 4, False), (30.0, 4, False), (100.0, 4, False)])
+def test_lad_cut_form_crafted_family(orc, x, m_exp, kept2):
+    # The cut form of theta (Sec. 3: a stencil whose largest chi-tilde is over
+    # H is discontinuous, and theta = 0 means a discontinuity): m = B_l for
+    # every x > H, the printed mapping (closed form above) for x <= H.  On the
+    # crafted family chi_2 is known in closed form, so the mask follows.
+    eps = 1e-6
+    s = math.sqrt(0.75 * x * eps)
+    f, m, mask, tr = orc.rec([0.0, 0.0, 0.0, 0.0, s], prob=CUT, trace=True)
+    assert abs(tr["x"] / x - 1.0) < 1e-12
+    assert m == m_exp
+    if x <= 10.0:
+        assert m == m_closed_form(x) and tr["theta"] == 1.0 / (1.0 + tr["x"] / 10.0)
+    else:
+        assert tr["theta"] == 0.0
+    g2 = (1.0 + x / (x + 1.0)) ** 6
+    chi2 = g2 / (2.0 * (1.0 + x) ** 6 + g2)
+    assert (chi2 >= 10.0 ** -m) == kept2
+    assert mask == (7 if kept2 else 3)
+
+
+def test_lad_cut_form_threshold_and_agreement(orc):
+    # Just above and below x = H the two forms differ only above: m jumps from
+    # B_l + floor(6 / 2) = 7 (theta = 1/2 at x = H) to B_l.  Away from H the
+    # cut form equals the printed one for x < H, and gives B_l for x > H.
+    eps = 1e-6
+    for x, m_cut, m_printed in [(np.nextafter(10.0, 0.0), 7, 7), (10.0 * (1 + 1e-12), 4, 6)]:
+        s = math.sqrt(0.75 * x * eps)
+        _, m, _, tr = orc.rec([0.0, 0.0, 0.0, 0.0, s], prob=CUT, trace=True)
+        _, mp, _ = orc.rec([0.0, 0.0, 0.0, 0.0, s])
+        assert (tr["x"] > 10.0) == (m == 4)
+        assert m == m_cut and mp == m_printed
+    rng = np.random.default_rng(8)
+    for _ in range(2000):
+        v = rng.normal(size=5) * 10.0 ** rng.uniform(-4, 1)
+        v[rng.integers(0, 5)] += rng.normal() * 10.0 ** rng.uniform(-3, 1)
+        fc, mc, kc, trc = orc.rec(v, prob=CUT, trace=True)
+        fp, mp, kp = orc.rec(v)
+        if trc["x"] > 10.0:
+            assert mc == 4 and trc["ct"] == 1e-4
+        else:
+            assert (fc, mc, kc) == (fp, mp, kp)
+
+
 # --------------------------------------------------------------------------
 # P6: characteristic decomposition
 # --------------------------------------------------------------------------
