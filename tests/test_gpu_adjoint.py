@@ -93,6 +93,11 @@ def test_rhs_adjoint_full_jacobian(torch, B, orc, name):
     ("2d_teno5a_130x67", lambda: (lambda p: (p, W.random_field(p, seed=34)))(
         W.uniform_problem(2, [130, 67], [0.0, 0.0], [1.0, 1.0], ["transmissive", "periodic"],
                           scheme="teno5a"))),
+    # the cut form of the LAD sensor (theta = 0 where max chi-tilde > H): the
+    # frozen ladder indices and masks are the cut form's
+    ("3d_random70x66x9_cut", lambda: (lambda p: (p, W.random_field(p, seed=32)))(
+        W.uniform_problem(3, [70, 66, 9], [0.0] * 3, [1.0] * 3,
+                          ["periodic", "reflective", "transmissive"], theta="cut"))),
 ])
 def test_rhs_adjoint_dot_product(torch, B, orc, name, mk):
     prob, U = mk()
