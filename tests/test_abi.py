@@ -53,8 +53,9 @@ int main(void) {
          offsetof(teno_grid, bc), offsetof(teno_grid, gamma), offsetof(teno_grid, H),
          offsetof(teno_grid, Bl), offsetof(teno_grid, eps), offsetof(teno_grid, flags),
          offsetof(teno_grid, a1), offsetof(teno_grid, xi));
-  printf("%zu %zu %zu %zu %zu\n", sizeof(teno_side), sizeof(teno_boundary),
-         offsetof(teno_boundary, gravity), offsetof(teno_side, state), offsetof(teno_grid, boundary_dev));
+  printf("%zu %zu %zu %zu %zu %zu %d %d\n", sizeof(teno_side), sizeof(teno_boundary),
+         offsetof(teno_boundary, gravity), offsetof(teno_side, state), offsetof(teno_grid, boundary_dev),
+         offsetof(teno_grid, theta), TENO_THETA_PRINTED, TENO_THETA_CUT);
   printf("%zu %zu %zu %zu %zu\n", sizeof(teno_ctrl), offsetof(teno_ctrl, alpha),
          offsetof(teno_ctrl, status), offsetof(teno_ctrl, nsteps), offsetof(teno_ctrl, active));
   return 0;
@@ -70,7 +71,7 @@ int main(void) {
     Sd, Bd = B.TenoSide, B.TenoBoundary
     assert [int(x) for x in out[1].split()] == [
         ctypes.sizeof(Sd), ctypes.sizeof(Bd), Bd.gravity.offset, Sd.state.offset,
-        G.boundary_dev.offset]
+        G.boundary_dev.offset, G.theta.offset, B.THETA["printed"], B.THETA["cut"]]
     assert [int(x) for x in out[2].split()] == [
         ctypes.sizeof(C), C.alpha.offset, C.status.offset, C.nsteps.offset, C.active.offset]
 
@@ -95,7 +96,7 @@ def test_workspace_bytes(B):
     dict(Bl=5, Bu=4), dict(Bu=21), dict(H=0.0), dict(eps=0.0),
     dict(scheme="teno5a", a1=3.0, a2=3.5), dict(scheme="teno5a", a1=21.0),
     dict(scheme="teno5a", cr=0.0), dict(scheme="teno5a", cr=1.2), dict(scheme="teno5a", xi=-1.0),
-    dict(scheme="teno5a", a2=-1.0)])
+    dict(scheme="teno5a", a2=-1.0), dict(theta=2), dict(theta=-1)])
 def test_validation_rejects_bad_grids(B, kw):
     try:
         g = _grid(B, **kw)
