@@ -390,6 +390,44 @@ def t_final_of(case):
     return None
 
 
+def sod_leg(args, B, W, torch):
+    """The Sod shock tube (N = 200, CFL 0.5, to t = 0.2): the whole run as
+    teno_step calls and as replays of a recorded graph of steps
+    (teno_runner), wall time of each and whether the end states agree bit
+    for bit.  On a grid this small every kernel is short, so launch cost
+    decides the time."""
+    prob, U = W.sod(200)
+    out = {"workload": "1D Sod shock tube N=200 on [0, 1], transmissive, CFL 0.5, to t = 0.2"}
+    ends = {}
+    for mode in ("steps", "graph", "steps", "graph"):   # second pass timed
+        S = B.Solver(prob)
+        u = torch.from_numpy(U.copy()).cuda()
+        S.init(0.0, 0.2, 0.5)
+        if mode == "graph":
+            S.run(u, 10, steps_per_graph=10)   # records the graph (untimed)
+            S.init(0.0, 0.2, 0.5)
+            u.copy_(torch.from_numpy(U))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        if mode == "graph":
+            S.run(u, 200, steps_per_graph=10)
+        else:
+            for _ in range(200):
+                S.step(u)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        c = S.read_ctrl()
+        ends[mode] = u.cpu()
+        out[mode] = {"wall_ms": round(wall * 1e3, 3), "steps": int(c.nsteps), "t": c.t,
+                     "status": int(c.status), "enqueued_steps": 200}
+    out["graph_over_steps_speedup"] = round(out["steps"]["wall_ms"] / out["graph"]["wall_ms"], 2)
+    out["bitwise_equal"] = bool(torch.equal(ends["steps"], ends["graph"]))
+    print(f"[bench] sod200 to t=0.2: steps {out['steps']['wall_ms']} ms, graph "
+          f"{out['graph']['wall_ms']} ms ({out['steps']['steps']} steps), bitwise "
+          f"{out['bitwise_equal']}", file=sys.stderr, flush=True)
+    return out
+
+
 def table2_leg(args, B, W, torch):
     """Per-step time of TENO5-LAD, TENO5 and TENO5-A on the Table 2 workloads
     (timed from the initial condition), with the parameter adjustments the
@@ -1182,6 +1220,7 @@ def main():
     }
     if not args.no_extras:
         out["schemes"] = schemes_leg(args, B, W, torch)
+        out["sod"] = sod_leg(args, B, W, torch)
         out["table2"] = table2_leg(args, B, W, torch)
         # the batched kernels are held off the GPU while an unexplained GPU
         # fault reported during their parity test has no cause

@@ -274,6 +274,34 @@ int teno_step(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
 int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
                     void* ws_dev, size_t ws_bytes, void* const* events, void* stream);
 
+/* Graph-replayed time stepping (eq 4.1-4.3 with the time-step control of
+ * teno_step).  A step never waits on the host -- dt, t and the status live
+ * in the device control block -- so a run of steps can be recorded once as a
+ * HIP graph and replayed, which removes the per-kernel launch cost that
+ * dominates small grids.
+ *
+ * teno_runner_create records steps_per_graph (1 .. 1000) consecutive
+ * teno_step calls on (g, U_dev, ctrl_dev, ws_dev) into a graph.  The grid
+ * description, the three device pointers and the workspace size are fixed
+ * at creation: the runner is valid while they are unchanged, and must be
+ * destroyed and re-created after any change to *g.  U_dev, ctrl_dev and
+ * ws_dev stay owned by the caller; the runner owns its graph and a private
+ * capture stream.  Returns TENO_ERR_ARG on an invalid grid, null pointer,
+ * short workspace or steps_per_graph out of range, TENO_ERR_DEVICE on a HIP
+ * error.
+ *
+ * teno_runner_run enqueues nsteps (>= 0) steps on `stream`: nsteps /
+ * steps_per_graph replays of the graph followed by the remaining steps
+ * launched one by one.  The result is bit-identical to nsteps teno_step
+ * calls, including the clipping at ctrl.t_end (later steps are no-ops) and
+ * the sticky status.  Runs on one runner must not overlap (they share U, the
+ * control block and the workspace). */
+typedef struct teno_runner teno_runner; /* opaque */
+int teno_runner_create(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev, void* ws_dev,
+                       size_t ws_bytes, int32_t steps_per_graph, teno_runner** out);
+int teno_runner_run(teno_runner* r, int64_t nsteps, void* stream);
+int teno_runner_destroy(teno_runner* r);
+
 /* ------------------------------------------------------------------------
  * Discrete adjoint.  With the cutoff flags delta_k of eq 2.14 (hence the
  * weights of eq 2.15) and the LF speeds held fixed, L is a smooth function of

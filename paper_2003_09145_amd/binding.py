@@ -93,6 +93,7 @@ assert CTRL_BYTES == 152
 SYMBOLS = ["teno_workspace_bytes", "teno_ctrl_init", "teno_ctrl_replay", "teno_ctrl_digest",
            "teno_rhs", "teno_rhs_noalloc", "teno_rhs_debug", "teno_sweep",
            "teno_selftest_arith", "teno_step", "teno_step_timed",
+           "teno_runner_create", "teno_runner_run", "teno_runner_destroy",
            "teno_adjoint_workspace_bytes", "teno_rhs_adjoint", "teno_step_adjoint",
            "teno_advect_workspace_bytes", "teno_advect_rhs", "teno_advect_step",
            "teno_batch_plan_create", "teno_batch_plan_destroy", "teno_batch_total_cells",
@@ -138,6 +139,13 @@ def lib():
         L.teno_step.restype = ctypes.c_int
         L.teno_step_timed.argtypes = [G, vp, vp, vp, ctypes.c_size_t, vp, vp]
         L.teno_step_timed.restype = ctypes.c_int
+        L.teno_runner_create.argtypes = [G, vp, vp, vp, ctypes.c_size_t, ctypes.c_int32,
+                                         ctypes.POINTER(vp)]
+        L.teno_runner_create.restype = ctypes.c_int
+        L.teno_runner_run.argtypes = [vp, ctypes.c_int64, vp]
+        L.teno_runner_run.restype = ctypes.c_int
+        L.teno_runner_destroy.argtypes = [vp]
+        L.teno_runner_destroy.restype = ctypes.c_int
         L.teno_adjoint_workspace_bytes.argtypes = [G]
         L.teno_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.teno_rhs_adjoint.argtypes = [G, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -432,6 +440,16 @@ class Solver:
         else:
             teno_step_timed(self.g, U, self.ctrl, self.ws, events)
 
+    def run(self, U, nsteps, steps_per_graph=10):
+        """nsteps teno_step calls on U, replayed from a HIP graph of
+        steps_per_graph steps (teno_runner; recorded on first use for this U)."""
+        r = self._runners.get((U.data_ptr(), steps_per_graph)) if hasattr(self, "_runners") else None
+        if r is None:
+            self._runners = getattr(self, "_runners", {})
+            r = Runner(self.g, U, self.ctrl, self.ws, steps_per_graph)
+            self._runners[(U.data_ptr(), steps_per_graph)] = r
+        r.run(nsteps)
+
     def read_ctrl(self) -> TenoCtrl:
         host = self.ctrl.cpu().numpy().tobytes()
         return TenoCtrl.from_buffer_copy(host)
@@ -440,6 +458,34 @@ class Solver:
         import torch
         buf = torch.frombuffer(bytearray(bytes(c)), dtype=torch.uint8)
         self.ctrl.copy_(buf.to(self.device))
+
+
+class Runner:
+    """A recorded run of steps_per_graph teno_step calls on fixed buffers
+    (teno_runner); keeps references to the tensors it was recorded on."""
+
+    def __init__(self, g, U, ctrl, ws, steps_per_graph=10):
+        self.g, self.U, self.ctrl, self.ws = g, U, ctrl, ws
+        h = ctypes.c_void_p()
+        _check(lib().teno_runner_create(ctypes.byref(g), _ptr(U), _ptr(ctrl), _ptr(ws),
+                                        ws.numel() * ws.element_size(), int(steps_per_graph),
+                                        ctypes.byref(h)),
+               "teno_runner_create")
+        self.h = h
+
+    def run(self, nsteps, stream=None):
+        _check(lib().teno_runner_run(self.h, int(nsteps), _stream(stream)), "teno_runner_run")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().teno_runner_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchPlan:

@@ -1019,3 +1019,82 @@ int teno_step_timed(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, si
 }
 
 }  // extern "C"
+
+// A recorded run of steps_per_graph steps on fixed buffers.  Every launch of
+// a step takes its arguments from the grid copy and the pointers held here,
+// and its dt, t and status from the device control block, so replays of the
+// graph continue the run exactly as further teno_step calls would.
+struct teno_runner {
+    teno_grid g;
+    double* U = nullptr;
+    teno_ctrl* ctrl = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t steps_per_graph = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int teno_runner_destroy(teno_runner* r) {
+    if (r == nullptr) return TENO_ERR_ARG;
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    if (r->cap) (void)hipStreamDestroy(r->cap);
+    delete r;
+    return TENO_OK;
+}
+
+int teno_runner_create(const teno_grid* g, double* U, teno_ctrl* ctrl, void* ws, size_t ws_bytes,
+                       int32_t steps_per_graph, teno_runner** out) {
+    if (out == nullptr || validate(g) != TENO_OK || U == nullptr || ctrl == nullptr ||
+        ws == nullptr || ws_bytes < workspace_bytes_impl(g) || steps_per_graph < 1 ||
+        steps_per_graph > 1000)
+        return TENO_ERR_ARG;
+    teno_runner* r = new teno_runner();
+    r->g = *g;
+    r->U = U;
+    r->ctrl = ctrl;
+    r->ws = ws;
+    r->ws_bytes = ws_bytes;
+    r->steps_per_graph = steps_per_graph;
+    // the steps are recorded on a private stream, so that no other work of
+    // the caller's stream is captured; thread-local mode leaves other
+    // threads' HIP calls alone
+    if (hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking) != hipSuccess) {
+        teno_runner_destroy(r);
+        return TENO_ERR_DEVICE;
+    }
+    if (hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        teno_runner_destroy(r);
+        return TENO_ERR_DEVICE;
+    }
+    int rc = TENO_OK;
+    for (int32_t k = 0; k < steps_per_graph && rc == TENO_OK; ++k)
+        rc = step_impl(&r->g, U, ctrl, ws, ws_bytes, nullptr, r->cap);
+    const hipError_t e = hipStreamEndCapture(r->cap, &r->graph);
+    if (rc != TENO_OK || e != hipSuccess ||
+        hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0) != hipSuccess) {
+        teno_runner_destroy(r);
+        return rc != TENO_OK ? rc : TENO_ERR_DEVICE;
+    }
+    *out = r;
+    return TENO_OK;
+}
+
+int teno_runner_run(teno_runner* r, int64_t nsteps, void* stream) {
+    if (r == nullptr || nsteps < 0) return TENO_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t done = 0;
+    for (; done + r->steps_per_graph <= nsteps; done += r->steps_per_graph)
+        if (hipGraphLaunch(r->exec, st) != hipSuccess) return TENO_ERR_DEVICE;
+    for (; done < nsteps; ++done) {
+        const int rc = step_impl(&r->g, r->U, r->ctrl, r->ws, r->ws_bytes, nullptr, st);
+        if (rc != TENO_OK) return rc;
+    }
+    return TENO_OK;
+}
+
+}  // extern "C"

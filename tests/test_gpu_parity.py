@@ -648,3 +648,73 @@ def test_huge_grid_64bit_offsets(torch, B, orc):
         Ubox = np.ascontiguousarray(_hash_field_np(ii, jj, kk))
         ref = orc.rhs_cells(box, Ubox, alpha.cpu().numpy(), np.array([3 * 49 + 3 * 7 + 3]))
         assert np.array_equal(got[s], ref[0]), (ix, jy, k, got[s], ref[0])
+
+
+# --------------------------------------------------------------------------
+# Graph-replayed steps (teno_runner): bit-identical to teno_step calls
+# --------------------------------------------------------------------------
+def test_runner_replays_match_steps(torch, B):
+    # Every replay is checked against eager steps on a copy, with eager steps
+    # of the runner's own buffers and host synchronizations in between
+    # (replays after the first must continue the run exactly), and the run
+    # crosses t_end inside a replay (the remaining steps are no-ops).
+    prob, U = W.sod(200)
+    t_end = 0.05
+    S_ref = B.Solver(prob)
+    S = B.Solver(prob)
+    u_ref = torch.from_numpy(U.copy()).cuda()
+    u = torch.from_numpy(U.copy()).cuda()
+    S_ref.init(0.0, t_end, 0.5)
+    S.init(0.0, t_end, 0.5)
+    R = B.Runner(S.g, u, S.ctrl, S.ws, steps_per_graph=7)
+    plan = [("graph", 7), ("eager", 2), ("graph", 14), ("graph", 3), ("eager", 1), ("graph", 21),
+            ("graph", 7)]
+    for kind, n in plan:
+        if kind == "graph":
+            R.run(n)
+        else:
+            for _ in range(n):
+                S.step(u)
+        for _ in range(n):
+            S_ref.step(u_ref)
+        torch.cuda.synchronize()
+        c, cr = S.read_ctrl(), S_ref.read_ctrl()
+        assert torch.equal(u, u_ref), (kind, n, c.nsteps)
+        assert (c.t, c.dt, c.nsteps, c.status) == (cr.t, cr.dt, cr.nsteps, cr.status)
+    print(f"[runner] sod200: {c.nsteps} steps to t = {c.t} (t_end {t_end}) bitwise equal "
+          f"to teno_step over {len(plan)} segments", flush=True)
+    assert c.t == t_end and c.nsteps < sum(n for _, n in plan)
+    R.close()
+
+
+@pytest.mark.parametrize("name,steps", [("2d_riemann3_96x80", 23), ("3d_random21x18x13_mixed", 12)])
+def test_runner_matches_oracle(torch, B, orc, name, steps):
+    prob, U = CASES[name]()
+    S = B.Solver(prob)
+    u = torch.from_numpy(U.copy()).cuda()
+    S.init(0.0, 1e9, 0.5)
+    S.run(u, steps, steps_per_graph=5)
+    torch.cuda.synchronize()
+    Uc = U.copy()
+    t = 0.0
+    for _ in range(steps):
+        Uc, t, dt, a9, st = orc.step(prob, Uc, 0.5, t, 1e9)
+    c = S.read_ctrl()
+    assert c.status == st == 0 and c.t == t and c.nsteps == steps
+    assert np.array_equal(u.cpu().numpy(), Uc)
+
+
+def test_runner_rejects_bad_arguments(torch, B):
+    prob, U = W.sod(50)
+    S = B.Solver(prob)
+    u = torch.from_numpy(U.copy()).cuda()
+    L = B.lib()
+    h = ctypes.c_void_p()
+    nb = S.ws.numel()
+    args = lambda spg, ws_bytes: (ctypes.byref(S.g), B._ptr(u), B._ptr(S.ctrl), B._ptr(S.ws),
+                                  ws_bytes, spg, ctypes.byref(h))
+    assert L.teno_runner_create(*args(0, nb)) == B.ERR_ARG
+    assert L.teno_runner_create(*args(1001, nb)) == B.ERR_ARG
+    assert L.teno_runner_create(*args(4, nb - 1)) == B.ERR_ARG
+    assert L.teno_runner_run(None, 3, None) == B.ERR_ARG
+    assert L.teno_runner_destroy(None) == B.ERR_ARG
