@@ -237,6 +237,11 @@ def test_lad_cut_form_parity(torch, B, orc, name, steps):
     lit.literal_decisions = True
     Rl, dl, _, _ = _gpu_rhs(torch, B, lit, U)
     assert np.array_equal(Rl, Rg) and np.array_equal(dl, dg)
+    # against the FMA-free oracle under the same form, flips counted
+    Ro, do = orc.rhs(prob, U, dump=True, literal=True)
+    _, _, fmax = orc.rhs_flux_abs(prob, U, literal=True, with_max=True)
+    _, lrel, nbad = compare_literal(prob, Rg, Ro, dg, do, fmax, name + " cut")
+    assert lrel <= REL and nbad <= max(8, 1e-3 * prob.ncell)
     Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
     Uc = U.copy()
     t = 0.0
@@ -266,6 +271,11 @@ def test_teno5a_parity(torch, B, orc, name, kw, steps):
     lit.literal_decisions = True
     Rl, dl, _, _ = _gpu_rhs(torch, B, lit, U)
     assert np.array_equal(Rl, Rg) and np.array_equal(dl, dg)
+    # against the FMA-free oracle under the same form, flips counted
+    Ro, do = orc.rhs(prob, U, dump=True, literal=True)
+    _, _, fmax = orc.rhs_flux_abs(prob, U, literal=True, with_max=True)
+    _, lrel, nbad = compare_literal(prob, Rg, Ro, dg, do, fmax, name + " cut")
+    assert lrel <= REL and nbad <= max(8, 1e-3 * prob.ncell)
     Ug, c = _gpu_steps(torch, B, prob, U, 0.5, 1e9, steps)
     Uc = U.copy()
     t = 0.0
