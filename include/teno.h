@@ -278,9 +278,9 @@ int teno_step_timed(const teno_grid* g, double* U_dev, teno_ctrl* ctrl_dev,
  * teno_step).  A step never waits on the host -- dt, t and the status live
  * in the device control block -- so a run of steps can be recorded once as a
  * HIP graph and replayed: the host then submits one graph per
- * steps_per_graph steps instead of every kernel of every step.  (On a small grid such as the
- * 200-cell Sod tube the kernels' own device time, not the host's launch
- * work, sets the pace, so the replays gain little there.)
+ * steps_per_graph steps instead of every kernel of every step.  (On a small
+ * grid such as the 200-cell Sod tube the kernels' own device time, not the
+ * host's launch work, sets the pace, so the replays gain little there.)
  *
  * teno_runner_create records steps_per_graph (1 .. 1000) consecutive
  * teno_step calls on (g, U_dev, ctrl_dev, ws_dev) into a graph.  The grid
